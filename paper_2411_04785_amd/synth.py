@@ -1,0 +1,187 @@
+"""Seeded synthetic inputs for dense 3-way CP workloads.
+
+This module only *draws* inputs: Gaussian factor matrices, CP-structured
+tensors (a sum of R outer products plus Gaussian noise), log-uniform slice
+magnitudes and open-loop request streams.  It holds none of the arithmetic
+being tested (no MTTKRP, Gram matrix, solve, normalisation or fit), so both
+the GPU path and the FP64 oracle may consume what it produces.
+
+Determinism: every array is a pure function of (workload seed, stream,
+index).  Tensor slices are drawn from a per-slice stream, so any mode-1
+slice X[i] can be regenerated on its own, which lets tests check sampled
+output rows of full-size runs without holding the whole tensor twice.
+
+Noise convention: ``noise_var`` is the *variance* of the additive
+N(0, var) noise (standard deviation sqrt(var)).
+"""
+
+from __future__ import annotations
+
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+BASE_SEED = 20241107
+
+# Independent random streams per workload.
+STREAM_FACTORS = 0   # true CP factors of the synthetic tensor
+STREAM_NOISE = 1     # additive Gaussian noise (one sub-stream per slice)
+STREAM_INIT = 2      # query / initial factors given to MTTKRP and CP-ALS
+STREAM_SCALES = 3    # per-slice magnitudes
+STREAM_REQUESTS = 4  # serving request stream
+
+
+@dataclass(frozen=True)
+class Workload:
+    """A dense 3-way CP workload.
+
+    dims:        (I, J, K) tensor shape, row-major with k fastest.
+    rank_true:   rank of the CP model the tensor is built from.
+    R:           number of columns of the factor matrices used by MTTKRP/ALS.
+    noise_var:   variance of the iid Gaussian noise added to every entry.
+    slice_log10: if set, (lo, hi): mode-1 slice i is multiplied by 10**u_i,
+                 u_i ~ U(lo, hi) (log-uniform magnitudes); no noise is added
+                 to such workloads unless noise_var > 0.
+    seed:        base seed; stream s uses seed + s.
+    """
+
+    name: str
+    dims: Tuple[int, int, int]
+    rank_true: int
+    R: int
+    noise_var: float
+    seed: int
+    slice_log10: Optional[Tuple[float, float]] = None
+    als_sweeps: int = 0
+
+
+# The workloads used by tests and the benchmark.  Seeds follow
+# BASE_SEED + 100 * n for the n-th workload (n = 1..5).
+WORKLOADS = {
+    "cp64_r8": Workload("cp64_r8", (64, 64, 64), 8, 8, 1e-6, BASE_SEED + 100),
+    "cp512_r32": Workload("cp512_r32", (512, 512, 512), 32, 32, 1e-4, BASE_SEED + 200,
+                          als_sweeps=10),
+    "cp1024_r64": Workload("cp1024_r64", (1024, 1024, 1024), 64, 64, 1e-3, BASE_SEED + 300),
+    "cp768_r128_sliced": Workload("cp768_r128_sliced", (768, 768, 768), 128, 128, 0.0,
+                                  BASE_SEED + 400, slice_log10=(-3.0, 3.0), als_sweeps=20),
+}
+
+
+def rng(seed: int, stream: int, *extra: int) -> np.random.Generator:
+    """PCG64 generator for (seed + stream, *extra)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed + stream, *extra])))
+
+
+def gaussian_factors(seed: int, stream: int, dims: Sequence[int], R: int,
+                     dtype=np.float64) -> List[np.ndarray]:
+    """Three iid N(0,1) factor matrices of shape (dims[n], R), row-major."""
+    g = rng(seed, stream)
+    return [g.standard_normal((int(d), R)).astype(dtype) for d in dims]
+
+
+def true_factors(w: Workload) -> List[np.ndarray]:
+    """FP64 factors A, B, C the workload's tensor is built from."""
+    return gaussian_factors(w.seed, STREAM_FACTORS, w.dims, w.rank_true, np.float64)
+
+
+def init_factors(w: Workload, R: Optional[int] = None) -> List[np.ndarray]:
+    """FP32 N(0,1) factors used as MTTKRP operands and as the CP-ALS start."""
+    return gaussian_factors(w.seed, STREAM_INIT, w.dims, R or w.R, np.float32)
+
+
+def slice_magnitudes(w: Workload) -> Optional[np.ndarray]:
+    """FP64 per-slice multipliers 10**u_i, u_i ~ U(lo, hi); None if unscaled."""
+    if w.slice_log10 is None:
+        return None
+    lo, hi = w.slice_log10
+    u = rng(w.seed, STREAM_SCALES).uniform(lo, hi, size=w.dims[0])
+    return np.power(10.0, u)
+
+
+def _slice(w: Workload, facs: List[np.ndarray], mags: Optional[np.ndarray], i: int) -> np.ndarray:
+    A, B, C = facs
+    a = A[i].copy()
+    if mags is not None:
+        a *= mags[i]
+    s = (B * a) @ C.T                      # sum_r a_r B(:,r) C(:,r)^T in FP64
+    if w.noise_var > 0.0:
+        noise = rng(w.seed, STREAM_NOISE, i).standard_normal(s.shape)
+        s += math.sqrt(w.noise_var) * noise
+    return s.astype(np.float32)
+
+
+def tensor_slices(w: Workload, i0: int, i1: int, out: Optional[np.ndarray] = None,
+                  threads: Optional[int] = None) -> np.ndarray:
+    """FP32 slices X[i0:i1] of the workload tensor, shape (i1-i0, J, K).
+
+    Each slice is built in FP64 from the true factors (times its magnitude,
+    if any) plus its own noise stream, then rounded to FP32.
+    """
+    facs = true_factors(w)
+    mags = slice_magnitudes(w)
+    _, J, K = w.dims
+    if out is None:
+        out = np.empty((i1 - i0, J, K), dtype=np.float32)
+
+    def work(i):
+        out[i - i0] = _slice(w, facs, mags, i)
+
+    nthr = threads or min(16, os.cpu_count() or 1)
+    if nthr <= 1 or i1 - i0 <= 1:
+        for i in range(i0, i1):
+            work(i)
+    else:
+        with ThreadPoolExecutor(nthr) as ex:
+            list(ex.map(work, range(i0, i1)))
+    return out
+
+
+def tensor(w: Workload, threads: Optional[int] = None) -> np.ndarray:
+    """The whole FP32 tensor of the workload, shape dims."""
+    return tensor_slices(w, 0, w.dims[0], threads=threads)
+
+
+def small_cp(dims: Sequence[int], rank: int, seed: int, noise_var: float = 0.0,
+             R: Optional[int] = None):
+    """A small ad-hoc CP tensor: returns (X fp32, true factors fp64, query factors fp32)."""
+    w = Workload("adhoc", tuple(int(d) for d in dims), rank, R or rank, noise_var, seed)
+    return tensor(w, threads=1), true_factors(w), init_factors(w)
+
+
+# --------------------------------------------------------------------------
+# Serving request stream
+# --------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Request:
+    """One decomposition request of the serving workload."""
+
+    rid: int
+    arrival_s: float                 # scheduled arrival time from stream start
+    dims: Tuple[int, int, int]
+    R: int
+    sweeps: int
+    workload: Workload               # tensor recipe (rank-R CP + noise)
+
+
+def make_requests(n: int = 2000, rate_per_s: float = 200.0, dim_lo: int = 32,
+                  dim_hi: int = 384, ranks=(8, 16, 32, 64), noise_var: float = 1e-4,
+                  sweeps: int = 10, seed: int = BASE_SEED + 500) -> List[Request]:
+    """Open-loop Poisson request stream: exponential gaps at ``rate_per_s``,
+    dims iid uniform on [dim_lo, dim_hi] per mode, R uniform over ``ranks``."""
+    g = rng(seed, STREAM_REQUESTS)
+    gaps = g.exponential(1.0 / rate_per_s, size=n)
+    t = np.cumsum(gaps) - gaps[0]
+    dims = g.integers(dim_lo, dim_hi + 1, size=(n, 3))
+    rs = g.choice(np.asarray(ranks), size=n)
+    out = []
+    for q in range(n):
+        d = tuple(int(x) for x in dims[q])
+        R = int(rs[q])
+        wl = Workload(f"req{q}", d, R, R, noise_var, seed + 1000 * (q + 1))
+        out.append(Request(q, float(t[q]), d, R, sweeps, wl))
+    return out
