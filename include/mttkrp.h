@@ -1,0 +1,218 @@
+/*
+ * libmttkrp -- dense 3-way MTTKRP and CP-ALS on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed.  For a dense tensor X of shape I x J x K (row-major,
+ * element (i,j,k) at offset (i*J + j)*K + k) and factor matrices
+ * A (I x R), B (J x R), C (K x R) (row-major, r fastest), the mode-n MTTKRP
+ * (matricised tensor times Khatri-Rao product) is
+ *
+ *     mode 0:  M(i,r) = sum_{j,k} X(i,j,k) B(j,r) C(k,r)      (I x R)
+ *     mode 1:  M(j,r) = sum_{i,k} X(i,j,k) A(i,r) C(k,r)      (J x R)
+ *     mode 2:  M(k,r) = sum_{i,j} X(i,j,k) A(i,r) B(j,r)      (K x R)
+ *
+ * i.e. M_n = X_(n) times the Khatri-Rao product of the other two factors.
+ * CP-ALS updates each factor from its normal equations A_n V = M_n with
+ * V = Hadamard product of the other two Gram matrices A_m^T A_m, then
+ * normalises its columns to unit 2-norm (the norms become lambda).  The
+ * paper this library accompanies (arXiv 2411.04785) has no passage on these
+ * operations; the definitions above are the standard ones.
+ *
+ * Conventions for every entry point:
+ *  - Data pointers are DEVICE pointers owned by the caller.  The library
+ *    never frees, reallocates or retains them after the call returns, except
+ *    inside the als_sweep graph cache (released by mtk_graph_reset or
+ *    mtk_destroy).  `fit_host` in als_sweep is the only host buffer.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    enqueued asynchronously on it; arguments are validated synchronously.
+ *  - Invalid arguments return MTK_EINVAL with a message in mtk_last_error
+ *    and enqueue nothing.  Errors detected on the device (a non-positive
+ *    Cholesky pivot) set a sticky status word that mtk_check returns.
+ *  - NaN / Inf inputs propagate to the outputs; they are not checked.
+ *  - A context is not thread-safe: use one per host thread.  All entry
+ *    points of one context must use the same device.
+ *  - The library never throws across the ABI.
+ */
+#ifndef MTTKRP_H_
+#define MTTKRP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mtk_ctx mtk_ctx;
+
+typedef enum {
+  MTK_OK = 0,
+  MTK_EINVAL = -1,        /* invalid argument (nothing was enqueued) */
+  MTK_ENOMEM = -2,        /* device allocation failed */
+  MTK_EHIP = -3,          /* a HIP runtime call failed (message in mtk_last_error) */
+  MTK_ENOTSPD = -4,       /* normal-equation matrix not positive definite */
+  MTK_EUNSUPPORTED = -5,  /* valid but unsupported combination */
+  MTK_EBUDGET = -6,       /* serving: request larger than the whole HBM budget */
+  MTK_EAGAIN = -7         /* serving: nothing finished yet */
+} mtk_status;
+
+/* Arithmetic of the contraction.  All paths accumulate in FP32.
+ *  MTK_FP32     : FP32 products (FP32 MFMA).
+ *  MTK_BF16X3   : each FP32 operand split into bf16 hi = bf16(x) and
+ *                 lo = bf16(x - hi); the product is hi*hi + hi*lo + lo*hi
+ *                 on bf16 MFMA (the lo*lo term, below 2^-16 relative, is
+ *                 dropped).
+ *  MTK_FP8_E4M3 : OCP e4m3 tensor with per mode-1 slice power-of-two scales
+ *                 (see mtk_quantize_fp8); the factor operand is quantised to
+ *                 e4m3 with a power-of-two scale per column. */
+typedef enum { MTK_FP32 = 0, MTK_BF16X3 = 1, MTK_FP8_E4M3 = 2 } mtk_prec;
+
+/* Dense tensor descriptor.
+ *  data      : device pointer; FP32 values (fmt MTK_FP32) or e4m3 codes, one
+ *              byte each (fmt MTK_FP8_E4M3), row-major (i, j, k), k fastest.
+ *  dims      : I, J, K (each >= 1, I*J*K < 2^40).
+ *  fmt       : MTK_FP32 or MTK_FP8_E4M3.
+ *  slice_exp : FP8 only: device int32[I]; the value of element (i,j,k) is
+ *              decode(code) * 2^slice_exp[i].  NULL for FP32.  */
+typedef struct {
+  const void* data;
+  int64_t dims[3];
+  int32_t fmt;
+  const int32_t* slice_exp;
+} mtk_tensor;
+
+/* Create a context on HIP device `device` (makes it current).  The context
+ * owns a workspace that grows on demand and a sticky device status word. */
+mtk_status mtk_create(mtk_ctx** ctx, int device);
+
+/* Destroy a context, its workspace and its graph cache.  NULL is a no-op. */
+mtk_status mtk_destroy(mtk_ctx* ctx);
+
+/* Message of the last failing call on this context ("" if none).  The
+ * string is owned by the context and valid until its next call. */
+const char* mtk_last_error(const mtk_ctx* ctx);
+
+/* Synchronise `stream`, then return and clear the sticky device status:
+ * MTK_OK, or MTK_ENOTSPD if a Cholesky pivot was <= 0 since the last check. */
+mtk_status mtk_check(mtk_ctx* ctx, void* stream);
+
+/* Reserve workspace for MTTKRPs / solves / sweeps up to these sizes, so
+ * later calls of at most this size allocate nothing.  Optional. */
+mtk_status mtk_reserve(mtk_ctx* ctx, const int64_t dims[3], int64_t R, int prec);
+
+/* FP8 tensor preparation (operand prep).  x: FP32 tensor of shape dims
+ * (device).  For each mode-1 slice i, e_i = min{ e : amax_i <= 448 * 2^e }
+ * (0 for an all-zero slice) is written to exp_out[i] and
+ * q_out = e4m3(x * 2^-e_i) with round-to-nearest-even, saturating to +-448,
+ * the sign kept for values that round to zero, NaN -> 0x7F.  q_out holds
+ * I*J*K bytes in the same order as x.  Bit-exact and deterministic. */
+mtk_status mtk_quantize_fp8(mtk_ctx* ctx, const float* x, const int64_t dims[3],
+                            uint8_t* q_out, int32_t* exp_out, void* stream);
+
+/* Mode-n MTTKRP (see top of file).
+ *  X        : tensor descriptor (device data).
+ *  factors  : host array of three device pointers A, B, C (FP32, row-major,
+ *             dims[n] x R).  factors[mode] is not read and may be NULL.
+ *  R        : 1 <= R <= 128.
+ *  mode     : 0, 1 or 2.
+ *  prec     : MTK_FP32 or MTK_BF16X3 for an FP32 tensor; MTK_FP8_E4M3 for
+ *             an FP8 tensor (the tensor's fmt decides; prec must match).
+ *  out      : device FP32, dims[mode] x R row-major; fully overwritten.
+ * The result is deterministic: the summation order depends only on
+ * (dims, R, mode, prec), never on timing or on other work on the device. */
+mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
+                  int64_t R, int mode, int prec, float* out, void* stream);
+
+/* Normal-equation update of one factor (FP64 on the device).
+ *  V = *_{m != mode} A_m^T A_m  (R x R, FP64, from the FP32 factors)
+ *  F = M V^{-1} by Cholesky of V and forward/back substitution (FP64)
+ *  lambda_out[r] = ||F(:,r)||_2 (FP64); factor_out = F(:,r)/lambda_r cast
+ *  to FP32 (a column with lambda_r == 0 is written unscaled).
+ *  factors    : three device pointers (factors[mode] not read, may be NULL).
+ *  dims, R    : as for mttkrp.
+ *  M          : device FP32 dims[mode] x R (an MTTKRP result).
+ *  factor_out : device FP32 dims[mode] x R; may alias factors[mode] or M.
+ *  lambda_out : device FP64[R].
+ * A pivot <= 0 sets MTK_ENOTSPD in the sticky status (see mtk_check); the
+ * outputs are then unspecified. */
+mtk_status gram_solve(mtk_ctx* ctx, const float* const factors[3], const int64_t dims[3],
+                      int64_t R, int mode, const float* M, float* factor_out,
+                      double* lambda_out, void* stream);
+
+/* Fit of a CP model: fit = 1 - ||X - [[lambda; A,B,C]]||_F / ||X||_F,
+ * from the explicit residual accumulated in FP64 on the device.  Writes the
+ * fit to *fit_host after synchronising the stream. */
+mtk_status mtk_fit(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
+                   const double* lambda, int64_t R, double* fit_host, void* stream);
+
+/* CP-ALS sweeps.  Each sweep updates modes 0, 1, 2 in order: mttkrp, then
+ * gram_solve in place into factors[mode] and lambda.  The factors given are
+ * used as the starting point (not normalised first); lambda (device FP64[R])
+ * is overwritten.  Calling again with the same buffers continues the
+ * iteration (10 sweeps == 5 + 5 sweeps, bitwise).  The sweep sequence is
+ * captured once into a HIP graph per (shape, R, prec, pointers, stream) and
+ * replayed.  If fit_host is not NULL, fit_host[s] receives the fit after
+ * sweep s (an extra residual pass per sweep).  Synchronises `stream` once
+ * at the end and returns the sticky status (MTK_OK or MTK_ENOTSPD). */
+mtk_status als_sweep(mtk_ctx* ctx, const mtk_tensor* X, float* const factors[3],
+                     double* lambda, int64_t R, int prec, int nsweeps, double* fit_host,
+                     void* stream);
+
+/* Drop every cached als_sweep graph of this context. */
+mtk_status mtk_graph_reset(mtk_ctx* ctx);
+
+/* ---------------------------------------------------------------------
+ * Serving: continuous batching of CP-ALS decompositions.
+ *
+ * A server owns a device, an HBM budget and a worker thread.  Requests
+ * (a host FP32 tensor, rank R, sweep count) are admitted in arrival order
+ * when their device bytes (tensor + factors + workspace) fit in the budget
+ * next to the requests already resident; each admitted request gets its
+ * own stream, so the sweeps of all resident requests overlap on the GPU.
+ * A request's result depends only on its own inputs (same kernels and
+ * summation order as a lone als_sweep call), never on what runs beside it.
+ * --------------------------------------------------------------------- */
+typedef struct mtk_server mtk_server;
+
+typedef struct {
+  int64_t id;              /* caller's request id */
+  int32_t status;          /* mtk_status of the request */
+  int32_t R;
+  int64_t dims[3];
+  double fit;              /* final fit (explicit residual) */
+  double t_submit;         /* seconds since server start: submit call */
+  double t_admit;          /* admitted to the device */
+  double t_done;           /* result copied back to host */
+} mtk_result;
+
+/* budget_bytes: device bytes the server may hold for resident requests.
+ * max_slots: most requests resident at once (>= 1). */
+mtk_status mtk_server_create(mtk_server** srv, int device, uint64_t budget_bytes,
+                             int max_slots);
+
+/* Submit one request.  x: HOST FP32 tensor (copied before return),
+ * init: three HOST FP32 factor matrices (copied), prec: MTK_FP32 or
+ * MTK_BF16X3.  factors_out (three host buffers dims[n] x R, may be NULL) and
+ * lambda_out (host FP64[R], may be NULL) receive the result; they must stay
+ * valid until the request is returned by mtk_server_poll.
+ * Returns MTK_EBUDGET if the request can never fit the budget. */
+mtk_status mtk_server_submit(mtk_server* srv, int64_t id, const float* x, const int64_t dims[3],
+                             int64_t R, int prec, int sweeps, const float* const init[3],
+                             float* const factors_out[3], double* lambda_out);
+
+/* Retrieve up to `cap` finished requests (oldest first).  Waits up to
+ * timeout_s seconds for at least one; returns the count in *n. */
+mtk_status mtk_server_poll(mtk_server* srv, mtk_result* out, int cap, int* n, double timeout_s);
+
+/* Stats: resident requests, bytes in use, peak bytes in use. */
+mtk_status mtk_server_stats(mtk_server* srv, int* resident, uint64_t* bytes_in_use,
+                            uint64_t* peak_bytes);
+
+/* Finish every submitted request, then stop the worker and free the device
+ * memory.  NULL is a no-op. */
+mtk_status mtk_server_destroy(mtk_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTTKRP_H_ */

@@ -1,0 +1,372 @@
+// C-ABI entry points of libmttkrp (declared in include/mttkrp.h).
+
+#include "mtk_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+namespace {
+
+using mtk::ContractPlan;
+
+struct GraphKey {
+  const void* X;
+  int64_t dims[3];
+  int fmt;
+  const void* slice_exp;
+  const void* f[3];
+  const void* lambda;
+  int R, prec, with_fit;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(X, dims[0], dims[1], dims[2], fmt, slice_exp, f[0], f[1], f[2], lambda, R, prec, with_fit) <
+           std::tie(o.X, o.dims[0], o.dims[1], o.dims[2], o.fmt, o.slice_exp, o.f[0], o.f[1], o.f[2], o.lambda, o.R,
+                    o.prec, o.with_fit);
+  }
+};
+
+struct GraphCache {
+  hipStream_t capture_stream = nullptr;
+  std::map<GraphKey, hipGraphExec_t> execs;
+  std::vector<hipGraph_t> graphs;
+};
+
+mtk_status fail(mtk_ctx* c, mtk_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+mtk_status hip_fail(mtk_ctx* c, hipError_t e, const char* where) {
+  return fail(c, MTK_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OR_FAIL(ctx, call)                          \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+bool dims_ok(const int64_t d[3]) {
+  if (d[0] < 1 || d[1] < 1 || d[2] < 1) return false;
+  if (d[0] > (1 << 30) || d[1] > (1 << 30) || d[2] > (1 << 30)) return false;
+  const double n = (double)d[0] * d[1] * d[2];
+  return n < 1099511627776.0;   // 2^40
+}
+
+mtk_status ensure_ws(mtk_ctx* c, size_t bytes, hipStream_t st) {
+  if (bytes <= c->ws_bytes) return MTK_OK;
+  // The old workspace may still be in use by queued work.
+  if (c->ws) {
+    HIP_OR_FAIL(c, hipStreamSynchronize(st));
+    HIP_OR_FAIL(c, hipDeviceSynchronize());
+    HIP_OR_FAIL(c, hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 1 << 20);
+  if (hipMalloc(&c->ws, want) != hipSuccess) {
+    (void)hipGetLastError();
+    c->ws = nullptr;
+    return fail(c, MTK_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  c->ws_bytes = want;
+  return MTK_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+mtk_status check_tensor(mtk_ctx* c, const mtk_tensor* X) {
+  if (!X) return fail(c, MTK_EINVAL, "X is NULL");
+  if (!X->data) return fail(c, MTK_EINVAL, "X->data is NULL");
+  if (!dims_ok(X->dims)) return fail(c, MTK_EINVAL, "X->dims out of range (each >= 1, product < 2^40)");
+  if (X->fmt != MTK_FP32 && X->fmt != MTK_FP8_E4M3) return fail(c, MTK_EINVAL, "X->fmt must be MTK_FP32 or MTK_FP8_E4M3");
+  if (X->fmt == MTK_FP8_E4M3 && !X->slice_exp) return fail(c, MTK_EINVAL, "FP8 tensor needs slice_exp");
+  if (X->fmt == MTK_FP32 && (reinterpret_cast<uintptr_t>(X->data) & 3)) return fail(c, MTK_EINVAL, "FP32 X->data not 4-byte aligned");
+  return MTK_OK;
+}
+
+mtk_status check_prec(mtk_ctx* c, const mtk_tensor* X, int prec) {
+  if (prec != MTK_FP32 && prec != MTK_BF16X3 && prec != MTK_FP8_E4M3) return fail(c, MTK_EINVAL, "unknown precision");
+  if (X->fmt == MTK_FP8_E4M3 && prec != MTK_FP8_E4M3) return fail(c, MTK_EINVAL, "FP8 tensor requires prec MTK_FP8_E4M3");
+  if (X->fmt == MTK_FP32 && prec == MTK_FP8_E4M3) return fail(c, MTK_EINVAL, "prec MTK_FP8_E4M3 requires an FP8 tensor (mtk_quantize_fp8)");
+  return MTK_OK;
+}
+
+size_t mttkrp_ws(const int64_t dims[3], int R, int mode, int prec) {
+  ContractPlan p = mtk::make_plan(dims, R, mode, prec, true);
+  ContractPlan q = mtk::make_plan(dims, R, mode, prec, false);
+  return std::max(mtk::contract_ws_bytes(p, prec), mtk::contract_ws_bytes(q, prec));
+}
+
+size_t sweep_scratch_bytes(const int64_t dims[3], int R, int prec) {
+  size_t b = 0;
+  for (int m = 0; m < 3; ++m) b = std::max(b, mttkrp_ws(dims, R, m, prec));
+  const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
+  b = std::max(b, mtk::solve_ws_bytes(maxdim, R));
+  b = std::max(b, mtk::fit_ws_bytes(dims));
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+mtk_status mtk_create(mtk_ctx** ctx, int device) {
+  if (!ctx) return MTK_EINVAL;
+  *ctx = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MTK_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return MTK_EHIP;
+  mtk_ctx* c = new (std::nothrow) mtk_ctx();
+  if (!c) return MTK_ENOMEM;
+  c->device = device;
+  if (hipMalloc(&c->d_status, 256) != hipSuccess || hipMemset(c->d_status, 0, 256) != hipSuccess) {
+    delete c;
+    return MTK_ENOMEM;
+  }
+  if (hipMalloc(&c->d_fit, 2 * sizeof(double)) != hipSuccess) {
+    (void)hipFree(c->d_status);
+    delete c;
+    return MTK_ENOMEM;
+  }
+  GraphCache* gc = new (std::nothrow) GraphCache();
+  if (!gc || hipStreamCreateWithFlags(&gc->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete gc;
+    (void)hipFree(c->d_status);
+    (void)hipFree(c->d_fit);
+    delete c;
+    return MTK_EHIP;
+  }
+  c->graph_cache = gc;
+  *ctx = c;
+  return MTK_OK;
+}
+
+mtk_status mtk_graph_reset(mtk_ctx* c) {
+  if (!c) return MTK_EINVAL;
+  GraphCache* gc = static_cast<GraphCache*>(c->graph_cache);
+  if (!gc) return MTK_OK;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : gc->execs) (void)hipGraphExecDestroy(kv.second);
+  for (hipGraph_t g : gc->graphs) (void)hipGraphDestroy(g);
+  gc->execs.clear();
+  gc->graphs.clear();
+  return MTK_OK;
+}
+
+mtk_status mtk_destroy(mtk_ctx* c) {
+  if (!c) return MTK_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  mtk_graph_reset(c);
+  GraphCache* gc = static_cast<GraphCache*>(c->graph_cache);
+  if (gc) {
+    if (gc->capture_stream) (void)hipStreamDestroy(gc->capture_stream);
+    delete gc;
+  }
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->d_status) (void)hipFree(c->d_status);
+  if (c->d_fit) (void)hipFree(c->d_fit);
+  delete c;
+  return MTK_OK;
+}
+
+const char* mtk_last_error(const mtk_ctx* c) { return c ? c->last_error.c_str() : "NULL context"; }
+
+mtk_status mtk_check(mtk_ctx* c, void* stream) {
+  if (!c) return MTK_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_OR_FAIL(c, hipStreamSynchronize(st));
+  int s = 0;
+  HIP_OR_FAIL(c, hipMemcpy(&s, c->d_status, sizeof(int), hipMemcpyDeviceToHost));
+  if (s != 0) {
+    HIP_OR_FAIL(c, hipMemset(c->d_status, 0, sizeof(int)));
+    if (s & mtk::kStatusNotSPD) return fail(c, MTK_ENOTSPD, "normal-equation matrix not positive definite");
+  }
+  return MTK_OK;
+}
+
+mtk_status mtk_reserve(mtk_ctx* c, const int64_t dims[3], int64_t R, int prec) {
+  if (!c || !dims) return fail(c, MTK_EINVAL, "NULL argument");
+  if (!dims_ok(dims)) return fail(c, MTK_EINVAL, "dims out of range");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
+  size_t b = round256((size_t)maxdim * R * sizeof(float)) + sweep_scratch_bytes(dims, (int)R, prec);
+  return ensure_ws(c, b, nullptr);
+}
+
+mtk_status mtk_quantize_fp8(mtk_ctx* c, const float* x, const int64_t dims[3], uint8_t* q_out, int32_t* exp_out,
+                            void* stream) {
+  if (!c) return MTK_EINVAL;
+  if (!x || !dims || !q_out || !exp_out) return fail(c, MTK_EINVAL, "NULL argument");
+  if (!dims_ok(dims)) return fail(c, MTK_EINVAL, "dims out of range");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipError_t e = mtk::launch_quantize_slices(x, dims[0], dims[1] * dims[2], q_out, exp_out,
+                                             static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "quantize");
+  return MTK_OK;
+}
+
+static mtk_status mttkrp_impl(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], int R, int mode,
+                              int prec, float* out, void* ws, hipStream_t st) {
+  const float* fr;     // fragment factor (inside the MFMA)
+  const float* wt;     // weight factor (epilogue)
+  if (mode == 0) { fr = factors[2]; wt = factors[1]; }
+  else if (mode == 1) { fr = factors[2]; wt = factors[0]; }
+  else { fr = factors[1]; wt = factors[0]; }
+  ContractPlan p = mtk::make_plan(X->dims, R, mode, prec, aligned16(X->data));
+  hipError_t e = mtk::launch_contract(p, prec, mode, X->data, X->slice_exp, fr, wt, out, ws, st);
+  if (e != hipSuccess) return hip_fail(c, e, "mttkrp launch");
+  return MTK_OK;
+}
+
+mtk_status mttkrp(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], int64_t R, int mode, int prec,
+                  float* out, void* stream) {
+  if (!c) return MTK_EINVAL;
+  mtk_status s = check_tensor(c, X);
+  if (s != MTK_OK) return s;
+  if ((s = check_prec(c, X, prec)) != MTK_OK) return s;
+  if (mode < 0 || mode > 2) return fail(c, MTK_EINVAL, "mode must be 0, 1 or 2");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  if (!factors || !out) return fail(c, MTK_EINVAL, "NULL factors or out");
+  for (int m = 0; m < 3; ++m)
+    if (m != mode && !factors[m]) return fail(c, MTK_EINVAL, "NULL factor pointer");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = ensure_ws(c, mttkrp_ws(X->dims, (int)R, mode, prec), st)) != MTK_OK) return s;
+  return mttkrp_impl(c, X, factors, (int)R, mode, prec, out, c->ws, st);
+}
+
+mtk_status gram_solve(mtk_ctx* c, const float* const factors[3], const int64_t dims[3], int64_t R, int mode,
+                      const float* M, float* factor_out, double* lambda_out, void* stream) {
+  if (!c) return MTK_EINVAL;
+  if (!factors || !dims || !M || !factor_out || !lambda_out) return fail(c, MTK_EINVAL, "NULL argument");
+  if (!dims_ok(dims)) return fail(c, MTK_EINVAL, "dims out of range");
+  if (mode < 0 || mode > 2) return fail(c, MTK_EINVAL, "mode must be 0, 1 or 2");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  for (int m = 0; m < 3; ++m)
+    if (m != mode && !factors[m]) return fail(c, MTK_EINVAL, "NULL factor pointer");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
+  mtk_status s = ensure_ws(c, mtk::solve_ws_bytes(maxdim, (int)R), st);
+  if (s != MTK_OK) return s;
+  hipError_t e = mtk::launch_gram_solve(factors, dims, (int)R, mode, M, factor_out, lambda_out, c->ws,
+                                        c->d_status, st);
+  if (e != hipSuccess) return hip_fail(c, e, "gram_solve launch");
+  return MTK_OK;
+}
+
+mtk_status mtk_fit(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], const double* lambda,
+                   int64_t R, double* fit_host, void* stream) {
+  if (!c) return MTK_EINVAL;
+  mtk_status s = check_tensor(c, X);
+  if (s != MTK_OK) return s;
+  if (!factors || !factors[0] || !factors[1] || !factors[2] || !lambda || !fit_host)
+    return fail(c, MTK_EINVAL, "NULL argument");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = ensure_ws(c, mtk::fit_ws_bytes(X->dims), st)) != MTK_OK) return s;
+  hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, factors, lambda, (int)R, c->d_fit, c->ws, st);
+  if (e != hipSuccess) return hip_fail(c, e, "fit launch");
+  double acc[2];
+  HIP_OR_FAIL(c, hipMemcpyAsync(acc, c->d_fit, sizeof(acc), hipMemcpyDeviceToHost, st));
+  HIP_OR_FAIL(c, hipStreamSynchronize(st));
+  *fit_host = 1.0 - std::sqrt(acc[0]) / std::sqrt(acc[1]);
+  return MTK_OK;
+}
+
+// One CP-ALS sweep (modes 0, 1, 2) enqueued on `st`, optionally followed by
+// the fit partial sums into c->d_fit.  M buffer and scratch come from ws.
+static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int R,
+                                int prec, bool with_fit, hipStream_t st) {
+  const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
+  float* M = static_cast<float*>(c->ws);
+  void* scratch = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
+  const float* cf[3] = {factors[0], factors[1], factors[2]};
+  for (int n = 0; n < 3; ++n) {
+    mtk_status s = mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st);
+    if (s != MTK_OK) return s;
+    hipError_t e = mtk::launch_gram_solve(cf, X->dims, R, n, M, factors[n], lambda, scratch, c->d_status, st);
+    if (e != hipSuccess) return hip_fail(c, e, "gram_solve launch");
+  }
+  if (with_fit) {
+    hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, R, c->d_fit, scratch, st);
+    if (e != hipSuccess) return hip_fail(c, e, "fit launch");
+  }
+  return MTK_OK;
+}
+
+mtk_status als_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int64_t R, int prec,
+                     int nsweeps, double* fit_host, void* stream) {
+  if (!c) return MTK_EINVAL;
+  mtk_status s = check_tensor(c, X);
+  if (s != MTK_OK) return s;
+  if ((s = check_prec(c, X, prec)) != MTK_OK) return s;
+  if (!factors || !factors[0] || !factors[1] || !factors[2] || !lambda) return fail(c, MTK_EINVAL, "NULL argument");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  if (nsweeps < 0) return fail(c, MTK_EINVAL, "nsweeps < 0");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
+  const size_t need = round256((size_t)maxdim * R * sizeof(float)) + sweep_scratch_bytes(X->dims, (int)R, prec);
+  if (c->ws_bytes < need) {
+    // A graph bakes in the workspace address: growing it invalidates them.
+    mtk_graph_reset(c);
+    if ((s = ensure_ws(c, need, st)) != MTK_OK) return s;
+  }
+  if (nsweeps == 0) return mtk_check(c, stream);
+
+  GraphCache* gc = static_cast<GraphCache*>(c->graph_cache);
+  const bool with_fit = fit_host != nullptr;
+  GraphKey key{};
+  key.X = X->data;
+  for (int m = 0; m < 3; ++m) { key.dims[m] = X->dims[m]; key.f[m] = factors[m]; }
+  key.fmt = X->fmt;
+  key.slice_exp = X->slice_exp;
+  key.lambda = lambda;
+  key.R = (int)R;
+  key.prec = prec;
+  key.with_fit = with_fit;
+  hipGraphExec_t exec = nullptr;
+  auto it = gc->execs.find(key);
+  if (it != gc->execs.end()) {
+    exec = it->second;
+  } else {
+    hipGraph_t g = nullptr;
+    HIP_OR_FAIL(c, hipStreamBeginCapture(gc->capture_stream, hipStreamCaptureModeThreadLocal));
+    s = enqueue_sweep(c, X, factors, lambda, (int)R, prec, with_fit, gc->capture_stream);
+    hipError_t ee = hipStreamEndCapture(gc->capture_stream, &g);
+    if (s != MTK_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (ee != hipSuccess) return hip_fail(c, ee, "hipStreamEndCapture");
+    ee = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (ee != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(c, ee, "hipGraphInstantiate");
+    }
+    gc->graphs.push_back(g);
+    gc->execs[key] = exec;
+  }
+  std::vector<double> acc(with_fit ? 2 * (size_t)nsweeps : 0);
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    HIP_OR_FAIL(c, hipGraphLaunch(exec, st));
+    if (with_fit)
+      HIP_OR_FAIL(c, hipMemcpyAsync(&acc[2 * (size_t)sw], c->d_fit, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  s = mtk_check(c, stream);
+  if (with_fit)
+    for (int sw = 0; sw < nsweeps; ++sw) fit_host[sw] = 1.0 - std::sqrt(acc[2 * sw]) / std::sqrt(acc[2 * sw + 1]);
+  return s;
+}
+
+}  // extern "C"

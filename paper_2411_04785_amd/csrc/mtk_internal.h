@@ -1,0 +1,74 @@
+// Internal declarations shared by the HIP sources of libmttkrp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/mttkrp.h"
+
+namespace mtk {
+
+// Largest factor rank the kernels are instantiated for (8 MFMA N-tiles of 16).
+constexpr int kMaxRank = 128;
+// Lanes per wavefront on CDNA.
+constexpr int kWave = 64;
+
+// Device-side sticky status bits (OR-ed into the context's status word).
+constexpr int kStatusNotSPD = 1;
+
+// Work decomposition of one contraction launch (see mttkrp_kernels.hip).
+struct ContractPlan {
+  int nM, nRed, nLoop, R;        // extents: output rows, reduction length, outer loop length
+  int64_t sM, sRed, sLoop;       // element strides of X along the three roles
+  int nt;                        // MFMA N-tiles (16 columns each) covering R
+  int nv;                        // reduction values per lane per tile
+  int kw;                        // reduction values per wave = 4 * nv
+  int wr;                        // waves of a workgroup along the reduction (1, 2 or 4)
+  int mt_per_wg;                 // M-tiles per workgroup = 4 / wr
+  int n_rg;                      // reduction groups = ceil(nRed / (wr * kw))
+  int n_mg;                      // M groups = ceil(ceil(nM / 16) / mt_per_wg)
+  int loop_block;                // outer-loop iterations per workgroup
+  int n_lb;                      // outer-loop blocks
+  int slices;                    // partial slices = n_rg * n_lb
+  bool vec;                      // 16-byte vector loads along a contiguous reduction
+  int64_t grid() const { return (int64_t)n_rg * n_mg * n_lb; }
+};
+
+// Launch the mode-n contraction.  prec: MTK_FP32 / MTK_BF16X3 / MTK_FP8_E4M3.
+// X_fmt tells how X is stored.  Writes `out` (nM x R FP32) using `ws`
+// (at least contract_ws_bytes) for partial sums and quantised fragments.
+size_t contract_ws_bytes(const ContractPlan& p, int prec);
+ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16);
+hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void* X,
+                           const int32_t* slice_exp, const float* frag_src,
+                           const float* weight, float* out, void* ws, hipStream_t st);
+
+// FP8 tensor preparation (per mode-1 slice power-of-two scaled e4m3).
+hipError_t launch_quantize_slices(const float* x, int64_t I, int64_t JK, uint8_t* q,
+                                  int32_t* exps, hipStream_t st);
+
+// FP64 Gram / solve pieces.
+size_t solve_ws_bytes(int64_t maxdim, int R);
+hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3], int R,
+                             int mode, const float* M, float* factor_out, double* lambda,
+                             void* ws, int* status, hipStream_t st);
+size_t fit_ws_bytes(const int64_t dims[3]);
+hipError_t launch_fit(const void* X, int fmt, const int32_t* slice_exp, const int64_t dims[3],
+                      const float* const factors[3], const double* lambda, int R,
+                      double* acc2 /* [2]: residual^2, norm^2 */, void* ws, hipStream_t st);
+
+}  // namespace mtk
+
+// The opaque context behind mtk_ctx* (C ABI).
+struct mtk_ctx {
+  int device = 0;
+  void* ws = nullptr;             // workspace (partials, fragments, solve scratch)
+  size_t ws_bytes = 0;
+  int* d_status = nullptr;        // sticky device status word
+  double* d_fit = nullptr;        // fit accumulators
+  std::string last_error;
+  void* graph_cache = nullptr;    // als_sweep graph cache (see api.hip)
+};

@@ -1,0 +1,589 @@
+// Dense 3-way MTTKRP on CDNA4 matrix cores.
+//
+// All three modes are one contraction pattern.  Write the tensor element as
+// X(m, red, loop) with element offset m*sM + red*sRed + loop*sLoop:
+//
+//   mode 0: m = i, red = k, loop = j   M(i,r) = sum_j B(j,r) sum_k X C(k,r)
+//   mode 1: m = j, red = k, loop = i   M(j,r) = sum_i A(i,r) sum_k X C(k,r)
+//   mode 2: m = k, red = j, loop = i   M(k,r) = sum_i A(i,r) sum_j X B(j,r)
+//
+// The Khatri-Rao row of the definition, W((loop, red), r) = F(loop,r) G(red,r),
+// factors into a "fragment" factor G (applied inside the MFMA along the
+// reduction) and a "weight" factor F (applied once per (loop, m, r) in the
+// epilogue).  Each W entry is thus generated implicitly and never stored:
+// the fragment of G a wave needs stays in registers as MFMA B-operands for
+// the whole kernel, and F is a per-column scale of each finished tile.
+//
+// Work decomposition.  A wave owns a reduction window of kw = 4*nv values,
+// an M-tile of 16 output rows and a block of loop iterations.  Per loop
+// iteration it streams the 16 x kw tile of X (A-operand, lane (m, g) holds
+// row m and the nv contiguous reduction values g*nv .. g*nv+nv-1 -- any
+// consistent pairing of A and B lane elements is a valid MFMA reduction
+// order), runs nt MFMA chains (one per 16 columns of R) into a fresh tile T,
+// and adds F(loop, r) * T into its accumulator.  Workgroups are 4 waves:
+// for modes 0/1 (contiguous reduction) up to 4 waves cover adjacent
+// reduction windows of the same rows and are summed through LDS in fixed
+// order; for mode 2 the 4 waves cover 4 adjacent M-tiles (64 consecutive k).
+// Each workgroup writes one partial slice; a second kernel sums the slices
+// in fixed order.  Every sum therefore has an order fixed by
+// (dims, R, mode, precision) alone, so results are bitwise reproducible.
+
+#include "mtk_internal.h"
+#include "fp8_codec.h"
+
+#include <algorithm>
+
+namespace mtk {
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f4;
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+
+struct KArgs {
+  const void* X;
+  const int32_t* slice_exp;   // FP8 tensor: per mode-1 slice exponent
+  const float* frag_src;      // fragment factor G, nRed x R (FP32 / BF16X3)
+  const uint8_t* frag_q;      // FP8: e4m3 codes of G, nRed x R
+  const int32_t* frag_exp;    // FP8: per-column exponent of G
+  const float* weight;        // weight factor F, nLoop x R
+  float* part;                // slices x nM x R (or the output when slices == 1)
+  int64_t sM, sRed, sLoop;
+  int nM, nRed, nLoop, R;
+  int wr, mt_per_wg, n_rg, n_mg, loop_block, n_lb;
+  int mode;
+};
+
+__device__ __forceinline__ f4 zero4() { return f4{0.f, 0.f, 0.f, 0.f}; }
+
+// ---------------------------------------------------------------------------
+// Per-precision element type of X and MFMA step shape.
+// ---------------------------------------------------------------------------
+template <int PREC> struct PrecT;
+template <> struct PrecT<MTK_FP32> { using XT = float; static constexpr int kStep = 1; };
+template <> struct PrecT<MTK_BF16X3> { using XT = float; static constexpr int kStep = 8; };
+template <> struct PrecT<MTK_FP8_E4M3> { using XT = uint8_t; static constexpr int kStep = 32; };
+
+// X tile registers of one lane: nv reduction values of one row.
+template <int PREC, int NV> struct XRegs;
+template <int NV> struct XRegs<MTK_FP32, NV> { float v[NV]; };
+template <int NV> struct XRegs<MTK_BF16X3, NV> { float v[NV]; };
+template <int NV> struct XRegs<MTK_FP8_E4M3, NV> { uint32_t w[NV / 4]; };
+
+// Load this lane's nv reduction values of tile row `m` (global offset `off`
+// of its first value).  `full` means the whole window and row are in range.
+template <int PREC, int NV, bool CONTIG, bool VEC>
+__device__ __forceinline__ void load_x(XRegs<PREC, NV>& x, const void* X, int64_t off,
+                                       int64_t sRed, bool row_ok, int red0, int nRed, bool full) {
+  if constexpr (PREC == MTK_FP8_E4M3) {
+    const uint8_t* p = static_cast<const uint8_t*>(X) + off;
+    if (CONTIG && VEC && full) {
+#pragma unroll
+      for (int q = 0; q < NV / 16; ++q) {
+        uint4 u = *reinterpret_cast<const uint4*>(p + q * 16);
+        x.w[4 * q + 0] = u.x; x.w[4 * q + 1] = u.y; x.w[4 * q + 2] = u.z; x.w[4 * q + 3] = u.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NV / 4; ++q) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          int e = 4 * q + b;
+          uint32_t v = 0;
+          if (row_ok && red0 + e < nRed) v = p[(int64_t)e * sRed];
+          w |= v << (8 * b);
+        }
+        x.w[q] = w;
+      }
+    }
+  } else {
+    const float* p = static_cast<const float*>(X) + off;
+    if (CONTIG && VEC && full) {
+#pragma unroll
+      for (int q = 0; q < NV / 4; ++q) {
+        float4 u = *reinterpret_cast<const float4*>(p + q * 4);
+        x.v[4 * q + 0] = u.x; x.v[4 * q + 1] = u.y; x.v[4 * q + 2] = u.z; x.v[4 * q + 3] = u.w;
+      }
+    } else if (full) {
+#pragma unroll
+      for (int e = 0; e < NV; ++e) x.v[e] = p[(int64_t)e * sRed];
+    } else {
+#pragma unroll
+      for (int e = 0; e < NV; ++e)
+        x.v[e] = (row_ok && red0 + e < nRed) ? p[(int64_t)e * sRed] : 0.f;
+    }
+  }
+}
+
+// bf16 round-to-nearest-even split of a binary32 value: hi = bf16(x),
+// lo = bf16(x - hi); x - hi is exact.
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = static_cast<__bf16>(x);
+  lo = static_cast<__bf16>(x - static_cast<float>(hi));
+}
+
+// Fragment of the factor G held by one lane for the whole kernel: for N-tile
+// t and MFMA step s, the values G(red0 + s*kStep + e, t*16 + n) for the
+// lane's element slots e (n = lane & 15, red0 = window start + g*nv).
+template <int PREC, int NT, int NV> struct Frag;
+template <int NT, int NV> struct Frag<MTK_FP32, NT, NV> { float f[NT][NV]; };
+template <int NT, int NV> struct Frag<MTK_BF16X3, NT, NV> { bf16x8 hi[NT][NV / 8]; bf16x8 lo[NT][NV / 8]; };
+// FP8: the factor is held as two e4m3 terms, hi = e4m3(G 2^-eh) and
+// lo = e4m3((G - hi 2^eh) 2^-el), with per-column exponents eh, el; scl holds
+// 2^eh and 2^el of the lane's column for every N-tile.
+template <int NT, int NV> struct Frag<MTK_FP8_E4M3, NT, NV> {
+  i32x8 q[NT][NV / 32];
+  i32x8 ql[NT][NV / 32];
+  float sh[NT], sl[NT];
+};
+
+template <int PREC, int NT, int NV>
+__device__ __forceinline__ void load_frag(Frag<PREC, NT, NV>& fr, const KArgs& a, int red0, int n) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 16 + n;
+    const bool col_ok = col < a.R;
+    if constexpr (PREC == MTK_FP32) {
+#pragma unroll
+      for (int e = 0; e < NV; ++e) {
+        const int red = red0 + e;
+        fr.f[t][e] = (col_ok && red < a.nRed) ? a.frag_src[(int64_t)red * a.R + col] : 0.f;
+      }
+    } else if constexpr (PREC == MTK_BF16X3) {
+#pragma unroll
+      for (int s = 0; s < NV / 8; ++s) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int red = red0 + s * 8 + e;
+          float v = (col_ok && red < a.nRed) ? a.frag_src[(int64_t)red * a.R + col] : 0.f;
+          __bf16 h, l;
+          split_bf16(v, h, l);
+          fr.hi[t][s][e] = h;
+          fr.lo[t][s][e] = l;
+        }
+      }
+    } else {
+      const int64_t plane = (int64_t)a.nRed * a.R;
+#pragma unroll
+      for (int s = 0; s < NV / 32; ++s) {
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+          uint32_t word = 0, wl = 0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int red = red0 + s * 32 + w * 4 + b;
+            const bool ok = col_ok && red < a.nRed;
+            const uint32_t v = ok ? a.frag_q[(int64_t)red * a.R + col] : 0u;
+            const uint32_t vl = ok ? a.frag_q[plane + (int64_t)red * a.R + col] : 0u;
+            word |= v << (8 * b);
+            wl |= vl << (8 * b);
+          }
+          fr.q[t][s][w] = static_cast<int>(word);
+          fr.ql[t][s][w] = static_cast<int>(wl);
+        }
+      }
+      fr.sh[t] = col_ok ? ldexpf(1.f, a.frag_exp[col]) : 0.f;
+      fr.sl[t] = col_ok ? ldexpf(1.f, a.frag_exp[a.R + col]) : 0.f;
+    }
+  }
+}
+
+// T[t] = X-tile (16 x kw) times fragment (kw x 16) for every N-tile t.
+template <int PREC, int NT, int NV>
+__device__ __forceinline__ void tile_mfma(f4 (&T)[NT], const XRegs<PREC, NV>& x,
+                                          const Frag<PREC, NT, NV>& fr) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) T[t] = zero4();
+  if constexpr (PREC == MTK_FP32) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        T[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.v[s], fr.f[t][s], T[t], 0, 0, 0);
+  } else if constexpr (PREC == MTK_BF16X3) {
+#pragma unroll
+    for (int s = 0; s < NV / 8; ++s) {
+      bf16x8 ah, al;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 h, l;
+        split_bf16(x.v[s * 8 + e], h, l);
+        ah[e] = h;
+        al[e] = l;
+      }
+      // Small cross terms first, then the leading hi*hi term.
+#pragma unroll
+      for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, fr.hi[t][s], T[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.lo[t][s], T[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.hi[t][s], T[t], 0, 0, 0);
+    }
+  } else {
+    f4 Tl[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) Tl[t] = zero4();
+#pragma unroll
+    for (int s = 0; s < NV / 32; ++s) {
+      i32x8 xq;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) xq[w] = static_cast<int>(x.w[s * 8 + w]);
+      // e4m3 x e4m3 (format code 0 for both), unit E8M0 scales (127 = 2^0).
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        T[t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(xq, fr.q[t][s], T[t], 0, 0, 0, 127, 0, 127);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        Tl[t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(xq, fr.ql[t][s], Tl[t], 0, 0, 0, 127, 0, 127);
+    }
+    // Back to the factor's units: column scales of the two terms.
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[t][v] = fmaf(T[t][v], fr.sh[t], Tl[t][v] * fr.sl[t]);
+  }
+}
+
+template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
+__global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
+  constexpr int KW = 4 * NV;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int m_l = lane & 15;      // A-operand row / B-operand column of this lane
+  const int g = lane >> 4;        // reduction element group of this lane
+
+  // Workgroup -> (reduction group, M group, loop block); the reduction group
+  // varies fastest so neighbouring workgroups read neighbouring windows.
+  int bid = blockIdx.x;
+  const int rg = bid % a.n_rg; bid /= a.n_rg;
+  const int mg = bid % a.n_mg; bid /= a.n_mg;
+  const int lb = bid;
+
+  const int wred = wave % a.wr;
+  const int wm = wave / a.wr;
+  const int win = rg * a.wr + wred;                   // reduction window of this wave
+  const int red_base = win * KW;
+  const int red0 = red_base + g * NV;                 // this lane's first reduction value
+  const int mt = mg * a.mt_per_wg + wm;               // M-tile of this wave
+  const int m0 = mt * 16;
+  const int row = m0 + m_l;
+  const bool row_ok = row < a.nM;
+  const bool tile_full = (m0 + 16 <= a.nM) && (red_base + KW <= a.nRed);
+
+  Frag<PREC, NT, NV> fr;
+  load_frag<PREC, NT, NV>(fr, a, red0, m_l);
+
+  f4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = zero4();
+
+  const int l0 = lb * a.loop_block;
+  const int l1 = min(a.nLoop, l0 + a.loop_block);
+  const int64_t off0 = (int64_t)(row_ok ? row : 0) * a.sM + (int64_t)red0 * a.sRed;
+
+  auto step = [&](const XRegs<PREC, NV>& x, int it) {
+    f4 T[NT];
+    tile_mfma<PREC, NT, NV>(T, x, fr);
+    float sc = 1.f;
+    if constexpr (PREC == MTK_FP8_E4M3) {
+      if (a.mode != 0) sc = ldexpf(1.f, a.slice_exp[it]);   // slice i = loop index
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = t * 16 + m_l;
+      const float w = col < a.R ? a.weight[(int64_t)it * a.R + col] * sc : 0.f;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[t][v] = fmaf(w, T[t][v], acc[t][v]);
+    }
+  };
+
+  if (l0 < l1) {
+    XRegs<PREC, NV> xa, xb;
+    load_x<PREC, NV, CONTIG, VEC>(xa, a.X, off0 + (int64_t)l0 * a.sLoop, a.sRed, row_ok, red0, a.nRed, tile_full);
+    for (int it = l0; it < l1; it += 2) {
+      if (it + 1 < l1)
+        load_x<PREC, NV, CONTIG, VEC>(xb, a.X, off0 + (int64_t)(it + 1) * a.sLoop, a.sRed, row_ok, red0, a.nRed, tile_full);
+      step(xa, it);
+      if (it + 1 < l1) {
+        if (it + 2 < l1)
+          load_x<PREC, NV, CONTIG, VEC>(xa, a.X, off0 + (int64_t)(it + 2) * a.sLoop, a.sRed, row_ok, red0, a.nRed, tile_full);
+        step(xb, it + 1);
+      }
+    }
+  }
+
+  // FP8 mode 0: each output row is a slice i; apply its power-of-two scale.
+  if constexpr (PREC == MTK_FP8_E4M3) {
+    if (a.mode == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int orow = m0 + g * 4 + v;
+        const float s = orow < a.nM ? ldexpf(1.f, a.slice_exp[orow]) : 0.f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t][v] *= s;
+      }
+    }
+  }
+
+  // Sum the waves that share an M-tile (adjacent reduction windows) in LDS,
+  // in fixed wave order, then write this workgroup's partial slice.
+  __shared__ float red_lds[4][NT * 4][64];
+  if (a.wr > 1) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red_lds[wave][t * 4 + v][lane] = acc[t][v];
+    __syncthreads();
+    if (wred != 0) return;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float s = red_lds[wave][t * 4 + v][lane];
+        for (int q = 1; q < a.wr; ++q) s += red_lds[wave + q][t * 4 + v][lane];
+        acc[t][v] = s;
+      }
+  }
+
+  const int slice = rg * a.n_lb + lb;
+  float* outp = a.part + (int64_t)slice * a.nM * a.R;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 16 + m_l;
+    if (col >= a.R) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int orow = m0 + g * 4 + v;
+      if (orow < a.nM) outp[(int64_t)orow * a.R + col] = acc[t][v];
+    }
+  }
+}
+
+// out[e] = sum over slices s = 0..S-1 (in this order) of part[s][e].
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int S,
+                                                            int64_t n, float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float s = part[e];
+  for (int q = 1; q < S; ++q) s += part[(int64_t)q * n + e];
+  out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// FP8 fragment preparation, per column r of G (nRed x R):
+//   eh_r = min{e : amax|G(:,r)| <= 448 * 2^e},  hi = e4m3(G(:,r) * 2^-eh_r)
+//   res  = G(:,r) - decode(hi) * 2^eh_r            (exact in binary32)
+//   el_r = min{e : amax|res| <= 448 * 2^e},     lo = e4m3(res * 2^-el_r)
+// Codes: q[0 .. nRed*R) = hi, q[nRed*R .. 2*nRed*R) = lo; ex[r] = eh_r,
+// ex[R + r] = el_r.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float e4m3_decode_dev(uint32_t c) {
+  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  const float v = e == 0 ? ldexpf((float)m, -9) : ldexpf(1.f + (float)m * 0.125f, (int)e - 7);
+  return (c & 0x80u) ? -v : v;
+}
+
+__device__ float block_max(float m, float* smax) {
+  smax[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const float r = smax[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void frag_quant_kernel(const float* __restrict__ G, int nRed, int R,
+                                                         uint8_t* __restrict__ q, int32_t* __restrict__ ex) {
+  const int r = blockIdx.x;
+  __shared__ float smax[256];
+  const int64_t plane = (int64_t)nRed * R;
+  float m = 0.f;
+  for (int i = threadIdx.x; i < nRed; i += 256) m = fmaxf(m, fabsf(G[(int64_t)i * R + r]));
+  const int eh = scale_exponent_dev(block_max(m, smax));
+  const float ih = ldexpf(1.f, -eh), sh = ldexpf(1.f, eh);
+  float mr = 0.f;
+  for (int i = threadIdx.x; i < nRed; i += 256) {
+    const float g = G[(int64_t)i * R + r];
+    const uint32_t c = e4m3_encode_dev(g * ih);
+    q[(int64_t)i * R + r] = static_cast<uint8_t>(c);
+    mr = fmaxf(mr, fabsf(g - e4m3_decode_dev(c) * sh));
+  }
+  const int el = scale_exponent_dev(block_max(mr, smax));
+  const float il = ldexpf(1.f, -el);
+  for (int i = threadIdx.x; i < nRed; i += 256) {
+    const float g = G[(int64_t)i * R + r];
+    const float res = g - e4m3_decode_dev(q[(int64_t)i * R + r]) * sh;
+    q[plane + (int64_t)i * R + r] = static_cast<uint8_t>(e4m3_encode_dev(res * il));
+  }
+  if (threadIdx.x == 0) {
+    ex[r] = eh;
+    ex[R + r] = el;
+  }
+}
+
+template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
+hipError_t launch_one(const KArgs& a, int64_t grid, hipStream_t st) {
+  hipLaunchKernelGGL((contract_kernel<PREC, NT, NV, CONTIG, VEC>), dim3((unsigned)grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int PREC, int NT, int NV>
+hipError_t dispatch_cv(const KArgs& a, const ContractPlan& p, hipStream_t st) {
+  if (p.sRed == 1) {
+    if (p.vec) return launch_one<PREC, NT, NV, true, true>(a, p.grid(), st);
+    return launch_one<PREC, NT, NV, true, false>(a, p.grid(), st);
+  }
+  return launch_one<PREC, NT, NV, false, false>(a, p.grid(), st);
+}
+
+// nv choices: FP32 / BF16X3 {8,16,32,64}; FP8 {32,64,128}.
+template <int PREC, int NT>
+hipError_t dispatch_nv(const KArgs& a, const ContractPlan& p, hipStream_t st) {
+  if constexpr (PREC == MTK_FP8_E4M3) {
+    switch (p.nv) {
+      case 32: return dispatch_cv<PREC, NT, 32>(a, p, st);
+      case 64: if constexpr (NT <= 4) return dispatch_cv<PREC, NT, 64>(a, p, st); break;
+      case 128: if constexpr (NT <= 2) return dispatch_cv<PREC, NT, 128>(a, p, st); break;
+    }
+  } else {
+    switch (p.nv) {
+      case 8: return dispatch_cv<PREC, NT, 8>(a, p, st);
+      case 16: if constexpr (NT <= 4) return dispatch_cv<PREC, NT, 16>(a, p, st); break;
+      case 32: if constexpr (NT <= 2) return dispatch_cv<PREC, NT, 32>(a, p, st); break;
+      case 64: if constexpr (NT <= 1) return dispatch_cv<PREC, NT, 64>(a, p, st); break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int PREC>
+hipError_t dispatch_nt(const KArgs& a, const ContractPlan& p, hipStream_t st) {
+  switch (p.nt) {
+    case 1: return dispatch_nv<PREC, 1>(a, p, st);
+    case 2: return dispatch_nv<PREC, 2>(a, p, st);
+    case 3: return dispatch_nv<PREC, 3>(a, p, st);
+    case 4: return dispatch_nv<PREC, 4>(a, p, st);
+    case 5: return dispatch_nv<PREC, 5>(a, p, st);
+    case 6: return dispatch_nv<PREC, 6>(a, p, st);
+    case 7: return dispatch_nv<PREC, 7>(a, p, st);
+    case 8: return dispatch_nv<PREC, 8>(a, p, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16) {
+  ContractPlan p{};
+  const int64_t I = dims[0], J = dims[1], K = dims[2];
+  p.R = R;
+  p.nt = (int)cdiv(R, 16);
+  if (mode == 0) { p.nM = (int)I; p.nRed = (int)K; p.nLoop = (int)J; p.sM = J * K; p.sRed = 1; p.sLoop = K; }
+  else if (mode == 1) { p.nM = (int)J; p.nRed = (int)K; p.nLoop = (int)I; p.sM = K; p.sRed = 1; p.sLoop = J * K; }
+  else { p.nM = (int)K; p.nRed = (int)J; p.nLoop = (int)I; p.sM = 1; p.sRed = K; p.sLoop = J * K; }
+
+  // Fragment registers per lane: nt*nv (FP32, BF16X3 hi+lo) or nt*nv/4 (FP8); keep <= 64.
+  int nv;
+  if (prec == MTK_FP8_E4M3) {
+    nv = 128;
+    while (nv > 32 && p.nt * nv / 4 > 64) nv /= 2;
+    while (nv > 32 && 4 * (nv / 2) >= p.nRed) nv /= 2;
+  } else {
+    nv = 64;
+    while (nv > 8 && p.nt * nv > 64) nv /= 2;
+    while (nv > 8 && 4 * (nv / 2) >= p.nRed) nv /= 2;
+  }
+  p.nv = nv;
+  p.kw = 4 * nv;
+  const int64_t windows = cdiv(p.nRed, p.kw);
+  if (p.sRed == 1) {
+    p.wr = windows >= 4 ? 4 : (windows >= 2 ? 2 : 1);
+  } else {
+    p.wr = 1;
+  }
+  p.mt_per_wg = 4 / p.wr;
+  p.n_rg = (int)cdiv(p.nRed, (int64_t)p.wr * p.kw);
+  p.n_mg = (int)cdiv(cdiv(p.nM, 16), p.mt_per_wg);
+
+  // Spread the outer loop over enough workgroups to fill 256 CUs several
+  // times, but keep the partial slices' traffic at a few percent of X.
+  const int64_t base = (int64_t)p.n_rg * p.n_mg;
+  const int64_t target = 2048;
+  int64_t n_lb = std::max<int64_t>(1, std::min<int64_t>(p.nLoop, cdiv(target, base)));
+  const double xbytes = (double)I * J * K * (prec == MTK_FP8_E4M3 ? 1.0 : 4.0);
+  const double slice_bytes = (double)p.nM * R * 4.0 * 2.0;
+  const double cap = std::max(0.03 * xbytes, 4.0 * 1024 * 1024);
+  while (n_lb > 1 && (double)p.n_rg * n_lb * slice_bytes > cap) n_lb = cdiv(n_lb, 2);
+  p.loop_block = (int)cdiv(p.nLoop, n_lb);
+  p.n_lb = (int)cdiv(p.nLoop, p.loop_block);
+  p.slices = p.n_rg * p.n_lb;
+  const int elem = prec == MTK_FP8_E4M3 ? 1 : 4;
+  p.vec = (p.sRed == 1) && x_aligned16 && ((int64_t)p.nRed * elem % 16 == 0);
+  return p;
+}
+
+size_t contract_ws_bytes(const ContractPlan& p, int prec) {
+  size_t b = 0;
+  if (p.slices > 1) b += (size_t)p.slices * p.nM * p.R * sizeof(float);
+  b = (b + 255) & ~(size_t)255;
+  if (prec == MTK_FP8_E4M3) {
+    b += (2 * (size_t)p.nRed * p.R + 255) & ~(size_t)255;
+    b += 256 + 2 * (size_t)p.R * sizeof(int32_t);
+  }
+  return b;
+}
+
+hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void* X,
+                           const int32_t* slice_exp, const float* frag_src, const float* weight,
+                           float* out, void* ws, hipStream_t st) {
+  KArgs a{};
+  a.X = X;
+  a.slice_exp = slice_exp;
+  a.frag_src = frag_src;
+  a.weight = weight;
+  a.sM = p.sM; a.sRed = p.sRed; a.sLoop = p.sLoop;
+  a.nM = p.nM; a.nRed = p.nRed; a.nLoop = p.nLoop; a.R = p.R;
+  a.wr = p.wr; a.mt_per_wg = p.mt_per_wg; a.n_rg = p.n_rg; a.n_mg = p.n_mg;
+  a.loop_block = p.loop_block; a.n_lb = p.n_lb;
+  a.mode = mode;
+  char* w = static_cast<char*>(ws);
+  size_t partial_bytes = 0;
+  if (p.slices > 1) {
+    a.part = reinterpret_cast<float*>(w);
+    partial_bytes = ((size_t)p.slices * p.nM * p.R * sizeof(float) + 255) & ~(size_t)255;
+  } else {
+    a.part = out;
+  }
+  if (prec == MTK_FP8_E4M3) {
+    uint8_t* q = reinterpret_cast<uint8_t*>(w + partial_bytes);
+    int32_t* ex = reinterpret_cast<int32_t*>(w + partial_bytes + ((2 * (size_t)p.nRed * p.R + 255) & ~(size_t)255));
+    hipLaunchKernelGGL(frag_quant_kernel, dim3(p.R), dim3(256), 0, st, frag_src, p.nRed, p.R, q, ex);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    a.frag_q = q;
+    a.frag_exp = ex;
+  }
+  hipError_t e;
+  switch (prec) {
+    case MTK_FP32: e = dispatch_nt<MTK_FP32>(a, p, st); break;
+    case MTK_BF16X3: e = dispatch_nt<MTK_BF16X3>(a, p, st); break;
+    case MTK_FP8_E4M3: e = dispatch_nt<MTK_FP8_E4M3>(a, p, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (p.slices > 1) {
+    const int64_t n = (int64_t)p.nM * p.R;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st,
+                       a.part, p.slices, n, out);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace mtk

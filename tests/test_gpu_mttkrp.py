@@ -1,0 +1,183 @@
+"""GPU parity of the HIP MTTKRP (through the C ABI) against the FP64 oracle.
+
+Bars (relative Frobenius error per result against the FP64 oracle on the same
+FP32 input bytes): FP32 <= 1e-5, bf16x3 <= 1e-5, FP8 e4m3 <= 3e-2 against the
+*unquantised* tensor.  The FP8 tensor codes and slice exponents must match the
+oracle's quantiser bit for bit.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_04785_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16x3": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2411_04785_amd.mttkrp import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _case(dims, R, seed, noise=1e-4):
+    w = synth.Workload("t", tuple(dims), max(1, min(R, 8)), R, noise, seed)
+    return synth.tensor(w, threads=4), synth.init_factors(w)
+
+
+def _run(ctx, X, facs, mode, prec):
+    from gpu_util import dev, host
+    out = ctx.mttkrp(dev(X), [dev(f) for f in facs], mode, prec)
+    ctx.check()
+    return host(out)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_cp64_r8_all_modes(ctx, prec, mode):
+    from gpu_util import rel
+    w = synth.WORKLOADS["cp64_r8"]
+    X = synth.tensor(w)
+    facs = synth.init_factors(w)
+    _say("cp64_r8", prec, mode)
+    got = _run(ctx, X, facs, mode, prec)
+    ref = oracle.mttkrp(X, facs, mode)
+    assert rel(got, ref) <= TOL[prec]
+
+
+RAGGED = [
+    ((37, 50, 29), 5),
+    ((1, 1, 1), 1),
+    ((3, 200, 7), 20),
+    ((130, 17, 300), 37),
+    ((33, 65, 129), 64),
+    ((20, 24, 260), 128),
+    ((17, 300, 18), 96),
+    ((64, 96, 128), 16),
+    ((5, 7, 1000), 33),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("dims,R", RAGGED)
+def test_ragged_shapes_and_ranks(ctx, prec, dims, R):
+    from gpu_util import rel
+    X, facs = _case(dims, R, seed=hash((dims, R)) % 1000)
+    for mode in range(3):
+        _say("ragged", dims, R, prec, mode)
+        got = _run(ctx, X, facs, mode, prec)
+        ref = oracle.mttkrp(X, facs, mode)
+        assert rel(got, ref) <= TOL[prec], (mode, rel(got, ref))
+
+
+def test_unaligned_tensor_pointer(ctx):
+    # A view starting one element in: 4-byte aligned only, so no 16-byte loads.
+    import torch
+    from gpu_util import dev, host, rel
+    from paper_2411_04785_amd.mttkrp import Context
+    X, facs = _case((9, 10, 12), 8, seed=5)
+    flat = np.concatenate([[0.0], X.ravel()]).astype(np.float32)
+    d = dev(flat)[1:]
+    for mode in range(3):
+        out = ctx.mttkrp(d, [dev(f) for f in facs], mode, "fp32", desc=Context.tensor_desc(d, dims=X.shape))
+        assert rel(host(out), oracle.mttkrp(X, facs, mode)) <= 1e-5
+
+
+def test_deterministic_bitwise(ctx):
+    from gpu_util import dev, host
+    X, facs = _case((96, 80, 200), 32, seed=7)
+    Xd, fd = dev(X), [dev(f) for f in facs]
+    for prec in ("fp32", "bf16x3"):
+        for mode in range(3):
+            a = host(ctx.mttkrp(Xd, fd, mode, prec))
+            b = host(ctx.mttkrp(Xd, fd, mode, prec))
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_closed_form_noise_free(ctx):
+    # X = [[A, B, C]] exactly (up to FP32 rounding of X): M_1 = A (B^T B * C^T C).
+    from gpu_util import dev, host, rel
+    w = synth.Workload("cf", (48, 40, 56), 6, 6, 0.0, 77)
+    X = synth.tensor(w)
+    A, B, C = synth.true_factors(w)
+    facs = [f.astype(np.float32) for f in (A, B, C)]
+    got = host(ctx.mttkrp(dev(X), [dev(f) for f in facs], 0, "bf16x3"))
+    F = [f.astype(np.float64) for f in facs]
+    closed = F[0] @ ((F[1].T @ F[1]) * (F[2].T @ F[2]))
+    assert rel(got, closed) <= 1e-5
+
+
+# ------------------------------------------------------------------ FP8 ---
+
+def _sliced_case(dims, R, seed):
+    w = synth.Workload("s", tuple(dims), R, R, 0.0, seed, slice_log10=(-3.0, 3.0))
+    return synth.tensor(w, threads=4), synth.init_factors(w)
+
+
+def test_fp8_quantize_bit_exact(ctx):
+    from gpu_util import dev, host
+    X, _ = _sliced_case((40, 33, 50), 16, seed=3)
+    X[0, 0, :5] = [0.0, -0.0, 1e-30, -1e-30, 448.0]
+    X[1] = 0.0
+    q, e = ctx.quantize_fp8(dev(X))
+    qo, eo = oracle.quantize_slices_e4m3(X)
+    assert np.array_equal(host(e), eo)
+    assert np.array_equal(host(q), qo)
+
+
+@pytest.mark.parametrize("dims,R", [((40, 33, 50), 16), ((64, 64, 160), 128), ((31, 70, 130), 40)])
+def test_fp8_mttkrp(ctx, dims, R):
+    from gpu_util import dev, host, rel
+    X, facs = _sliced_case(dims, R, seed=11)
+    Xd = dev(X)
+    q, e = ctx.quantize_fp8(Xd)
+    qo, eo = oracle.quantize_slices_e4m3(X)
+    Xq = oracle.dequantize_slices_e4m3(qo, eo)
+    for mode in range(3):
+        _say("fp8", dims, R, mode)
+        got = host(ctx.mttkrp(q, [dev(f) for f in facs], mode, "fp8", slice_exp=e))
+        ref = oracle.mttkrp(X, facs, mode)
+        assert rel(got, ref) <= 3e-2
+        # Against the dequantised tensor only the factor's two-term e4m3
+        # rounding (about 2^-8 relative per entry) remains.
+        assert rel(got, oracle.mttkrp(Xq, facs, mode)) <= 5e-3
+        # Worst output row: per-slice scaling keeps the 1e-3 slices as accurate
+        # as the 1e3 ones (an underflowed slice would show an error near 1).
+        if mode == 0:
+            rr = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            assert rr.max() <= 0.1
+
+
+# --------------------------------------------------------- ABI errors ---
+
+def test_abi_errors(ctx):
+    import torch
+    from gpu_util import dev
+    from paper_2411_04785_amd.mttkrp import MtkError, MTK_EINVAL
+    X, facs = _case((8, 9, 10), 4, seed=1)
+    Xd, fd = dev(X), [dev(f) for f in facs]
+    with pytest.raises(MtkError) as ei:
+        ctx.mttkrp(Xd, fd, 3, "fp32")
+    assert ei.value.status == MTK_EINVAL
+    with pytest.raises(MtkError):
+        ctx.mttkrp(Xd, fd, 0, "fp32", R=129)
+    with pytest.raises(MtkError):
+        ctx.mttkrp(Xd, fd, 0, "fp8")             # FP32 tensor with FP8 precision
+    with pytest.raises(MtkError):
+        ctx.mttkrp(Xd, [fd[0], None, fd[2]], 0, "fp32")
+    ok = ctx.mttkrp(Xd, [None, fd[1], fd[2]], 0, "fp32")   # factors[mode] may be NULL
+    assert ok.shape == (8, 4)
