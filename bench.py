@@ -105,8 +105,9 @@ def main():
     ctx = Context(0)
     Xd = torch.from_numpy(X).to(dev)
     slice_exp = None
+    Xt = None
     if prec == "fp8":
-        Xq, slice_exp = ctx.quantize_fp8(Xd)
+        Xq, slice_exp, Xt = ctx.quantize_fp8(Xd, transposed=True)
         torch.cuda.synchronize()
         Xrun = Xq
     else:
@@ -118,13 +119,13 @@ def main():
     mode_ms = []
     outs = []
     for mode in range(3):
-        out = ctx.mttkrp(Xrun, f0, mode, prec, slice_exp=slice_exp)
+        out = ctx.mttkrp(Xrun, f0, mode, prec, slice_exp=slice_exp, X_t=Xt)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         for _ in range(args.mode_reps):
-            ctx.mttkrp(Xrun, f0, mode, prec, out=out, slice_exp=slice_exp)
+            ctx.mttkrp(Xrun, f0, mode, prec, out=out, slice_exp=slice_exp, X_t=Xt)
         ev1.record(stream)
         ev1.synchronize()
         mode_ms.append(ev0.elapsed_time(ev1) / args.mode_reps)
@@ -146,18 +147,18 @@ def main():
     fd = [f.clone() for f in f0]
     lam = torch.ones(R, dtype=torch.float64, device=dev)
     ctx.reserve(w.dims, R, prec)
-    ctx.als_sweep(Xrun, fd, lam, max(1, args.warmup), prec, slice_exp=slice_exp)
+    ctx.als_sweep(Xrun, fd, lam, max(1, args.warmup), prec, slice_exp=slice_exp, X_t=Xt)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
     ev0.record(stream)
-    ctx.als_sweep(Xrun, fd, lam, args.steps, prec, slice_exp=slice_exp)
+    ctx.als_sweep(Xrun, fd, lam, args.steps, prec, slice_exp=slice_exp, X_t=Xt)
     ev1.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     ms_step = ev0.elapsed_time(ev1) / args.steps
-    fit = ctx.fit(Xrun, fd, lam, slice_exp=slice_exp)
+    fit = ctx.fit(Xrun, fd, lam, slice_exp=slice_exp, X_t=Xt)
     log(f"[bench] {args.steps} sweeps: {ms_step:.3f} ms/sweep (wall {t_wall:.3f} s), fit {fit:.6f}")
 
     flop_mttkrp = 2.0 * I * J * K * R

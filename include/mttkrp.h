@@ -62,19 +62,25 @@ typedef enum {
  *                 on bf16 MFMA (the lo*lo term, below 2^-16 relative, is
  *                 dropped).
  *  MTK_FP8_E4M3 : OCP e4m3 tensor with per mode-1 slice power-of-two scales
- *                 (see mtk_quantize_fp8); the factor operand is quantised to
- *                 e4m3 with a power-of-two scale per column. */
+ *                 (see mtk_quantize_fp8) on e4m3 MFMA; the factor inside the
+ *                 contraction is held as two e4m3 terms, hi = e4m3(g 2^-eh)
+ *                 and lo = e4m3((g - hi 2^eh) 2^-el), with power-of-two
+ *                 scales eh, el per column (about 2^-8 relative). */
 typedef enum { MTK_FP32 = 0, MTK_BF16X3 = 1, MTK_FP8_E4M3 = 2 } mtk_prec;
 
 /* Dense tensor descriptor.
  *  data      : device pointer; FP32 values (fmt MTK_FP32) or e4m3 codes, one
  *              byte each (fmt MTK_FP8_E4M3), row-major (i, j, k), k fastest.
+ *  data_t    : FP8 only, optional (may be NULL): the same codes with every
+ *              mode-1 slice transposed, element (i,j,k) at (i*K + k)*J + j
+ *              (see mtk_quantize_fp8).  When present, mode 2 reads it.
  *  dims      : I, J, K (each >= 1, I*J*K < 2^40).
  *  fmt       : MTK_FP32 or MTK_FP8_E4M3.
  *  slice_exp : FP8 only: device int32[I]; the value of element (i,j,k) is
  *              decode(code) * 2^slice_exp[i].  NULL for FP32.  */
 typedef struct {
   const void* data;
+  const void* data_t;
   int64_t dims[3];
   int32_t fmt;
   const int32_t* slice_exp;
@@ -101,12 +107,15 @@ mtk_status mtk_reserve(mtk_ctx* ctx, const int64_t dims[3], int64_t R, int prec)
 
 /* FP8 tensor preparation (operand prep).  x: FP32 tensor of shape dims
  * (device).  For each mode-1 slice i, e_i = min{ e : amax_i <= 448 * 2^e }
- * (0 for an all-zero slice) is written to exp_out[i] and
- * q_out = e4m3(x * 2^-e_i) with round-to-nearest-even, saturating to +-448,
- * the sign kept for values that round to zero, NaN -> 0x7F.  q_out holds
- * I*J*K bytes in the same order as x.  Bit-exact and deterministic. */
+ * (0 for an all-zero slice; e_i is kept within [-126, 119]) is written to
+ * exp_out[i] and q_out = e4m3(x * 2^-e_i) with round-to-nearest-even,
+ * saturating to +-448, the sign kept for values that round to zero,
+ * NaN -> 0x7F.  q_out holds I*J*K bytes in the same order as x.  If qt_out
+ * is not NULL it receives the same codes with each slice transposed
+ * (element (i,j,k) at (i*K + k)*J + j), the layout mtk_tensor.data_t takes.
+ * Bit-exact and deterministic. */
 mtk_status mtk_quantize_fp8(mtk_ctx* ctx, const float* x, const int64_t dims[3],
-                            uint8_t* q_out, int32_t* exp_out, void* stream);
+                            uint8_t* q_out, uint8_t* qt_out, int32_t* exp_out, void* stream);
 
 /* Mode-n MTTKRP (see top of file).
  *  X        : tensor descriptor (device data).
@@ -124,7 +133,7 @@ mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[
 
 /* Normal-equation update of one factor (FP64 on the device).
  *  V = *_{m != mode} A_m^T A_m  (R x R, FP64, from the FP32 factors)
- *  F = M V^{-1} by Cholesky of V and forward/back substitution (FP64)
+ *  V = L L^T (Cholesky), V^{-1} = L^{-T} L^{-1}, F = M V^{-1} (FP64)
  *  lambda_out[r] = ||F(:,r)||_2 (FP64); factor_out = F(:,r)/lambda_r cast
  *  to FP32 (a column with lambda_r == 0 is written unscaled).
  *  factors    : three device pointers (factors[mode] not read, may be NULL).

@@ -3,36 +3,45 @@
 // Given the FP32 factors and the FP32 MTTKRP M (n x R) of mode `mode`:
 //   V = G_a * G_b (Hadamard), G_m = A_m^T A_m over the two other modes (FP64)
 //   V = L L^T (Cholesky, FP64; a pivot <= 0 sets the sticky NOT-SPD status)
-//   F = M V^{-1}: per row, forward substitution with L then back
-//       substitution with L^T (FP64)
+//   F = M V^{-1} by two triangular solves per row, G L^T = M and F L = G (FP64)
 //   lambda_r = ||F(:,r)||_2, factor = F(:,r) / lambda_r cast to FP32.
 // Every reduction runs in a fixed order, so the update is deterministic.
 
 #include "mtk_internal.h"
 
+#include <algorithm>
+
 namespace mtk {
 namespace {
 
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-constexpr int kRowsPerBlock = 2048;   // rows summed by one Gram / norm partial
+// Rows summed by one Gram partial: at least 128, and at most 64 partials.
+__host__ __device__ inline int64_t gram_rows(int64_t n) { const int64_t r = cdiv(n, 64); return r > 128 ? r : 128; }
+// Rows handled by one workgroup of the apply / normalise kernels (<= 256 groups).
+__host__ __device__ inline int64_t apply_rows(int64_t n) { const int64_t r = cdiv(n, 256); return r > 64 ? r : 64; }
 
-// part[rb][r][s] = sum over rows i of block rb of F(i,r) F(i,s), FP64.
-// Block (tile, rb), 256 threads = 16 x 16 entries of a 16 x 16 tile.
-__global__ __launch_bounds__(256) void gram_partial_kernel(const float* __restrict__ F, int64_t n, int R,
-                                                           int tiles_1d, double* __restrict__ part) {
-  const int tile = blockIdx.x;
+// part[f][rb][r][s] = sum over rows i of block rb of F_f(i,r) F_f(i,s), FP64,
+// for the two factors f = 0, 1.  Block (16x16 tile, rb, f); 256 threads.
+__global__ __launch_bounds__(256) void gram_partial_kernel(const float* __restrict__ F0, int64_t n0,
+                                                           const float* __restrict__ F1, int64_t n1, int R,
+                                                           int tiles_1d, int nrb_max, double* __restrict__ part) {
+  const int f = blockIdx.z;
+  const float* F = f ? F1 : F0;
+  const int64_t n = f ? n1 : n0;
+  const int64_t rows = gram_rows(n);
   const int rb = blockIdx.y;
+  const int64_t i0 = (int64_t)rb * rows;
+  if (i0 >= n) return;
+  const int64_t i1 = min(n, i0 + rows);
+  const int tile = blockIdx.x;
   const int tr = tile / tiles_1d, ts = tile % tiles_1d;
   const int r = tr * 16 + (threadIdx.x >> 4);
   const int s = ts * 16 + (threadIdx.x & 15);
-  __shared__ float rows_r[64][16];
-  __shared__ float rows_s[64][16];
-  const int64_t i0 = (int64_t)rb * kRowsPerBlock;
-  const int64_t i1 = min(n, i0 + kRowsPerBlock);
+  __shared__ float rows_r[64][17];
+  __shared__ float rows_s[64][17];
   double acc = 0.0;
   for (int64_t c0 = i0; c0 < i1; c0 += 64) {
-    // Stage 64 rows x 16 columns of both column groups.
     for (int e = threadIdx.x; e < 64 * 16; e += 256) {
       const int ii = e >> 4, cc = e & 15;
       const int64_t i = c0 + ii;
@@ -46,151 +55,257 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const float* __restri
       acc = fma((double)rows_r[ii][threadIdx.x >> 4], (double)rows_s[ii][threadIdx.x & 15], acc);
     __syncthreads();
   }
-  if (r < R && s < R) part[((int64_t)rb * R + r) * R + s] = acc;
+  if (r < R && s < R) part[(((int64_t)f * nrb_max + rb) * R + r) * R + s] = acc;
 }
 
-// V[r][s] = (sum_rb pa[rb][r][s]) * (sum_rb pb[rb][r][s]), fixed order.
-__global__ __launch_bounds__(256) void hadamard_kernel(const double* __restrict__ pa, int nra,
-                                                       const double* __restrict__ pb, int nrb, int R,
-                                                       double* __restrict__ V) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= R * R) return;
-  double a = 0.0, b = 0.0;
-  for (int q = 0; q < nra; ++q) a += pa[(int64_t)q * R * R + e];
-  for (int q = 0; q < nrb; ++q) b += pb[(int64_t)q * R * R + e];
-  V[e] = a * b;
+// Make this wave's LDS writes visible to its other lanes before they read.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
-
-// Cholesky V = L L^T of one R x R matrix by a single workgroup, right-looking,
-// packed lower triangle in LDS.  Writes L (packed) to Lg.  On a pivot <= 0
-// (or NaN) sets kStatusNotSPD in *status and stops.
-__global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict__ V, int R,
-                                                       double* __restrict__ Lg, int* __restrict__ status) {
-  extern __shared__ double P[];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < R * R; e += 256) {
-    const int i = e / R, j = e % R;
-    if (j <= i) P[tri(i, j)] = V[e];
+// One workgroup: V = G_0 * G_1 (Hadamard of the summed Gram partials) and
+// its Cholesky factor V = L L^T, FP64 in LDS.  Writes L (Rp x Rp, lower,
+// zero above the diagonal) to Lg and 1 / L(r,r) to dinv.  A pivot <= 0 (or
+// NaN) sets kStatusNotSPD and stops.
+//
+// V is padded to Rp = 16*ceil(R/16) with an identity block (whose factor is
+// an identity block).  Blocked right-looking with 16 x 16 blocks: wave 0
+// factors the diagonal block (16 wave-synchronous steps), every thread then
+// solves whole rows of the panel (L21 = A21 L11^{-T}), and the trailing lower
+// triangle is updated (A22 -= L21 L21^T) in 2 x 2 register tiles.  Every sum
+// runs in a fixed order: the factor is deterministic.
+__global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict__ part, int nr0, int nr1,
+                                                       int nrb_max, int R, double* __restrict__ Lg,
+                                                       double* __restrict__ dinv, int* __restrict__ status) {
+  extern __shared__ double lds[];
+  const int Rp = (R + 15) & ~15;
+  const int nb = Rp / 16;
+  const int ld = Rp + 1;
+  double* S = lds;                                   // Rp x ld
+  __shared__ int failed;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t RR = (int64_t)R * R;
+  if (tid == 0) failed = 0;
+  for (int e = tid; e < Rp * Rp; e += 256) {
+    const int i = e / Rp, j = e % Rp;
+    double v;
+    if (i < R && j < R) {
+      double a = 0.0, b = 0.0;
+      const int64_t o = (int64_t)i * R + j;
+      // Unrolled so the loads are in flight together; the adds keep index order.
+#pragma unroll 8
+      for (int q = 0; q < nr0; ++q) a += part[(int64_t)q * RR + o];
+#pragma unroll 8
+      for (int q = 0; q < nr1; ++q) b += part[((int64_t)nrb_max + q) * RR + o];
+      v = a * b;
+    } else {
+      v = (i == j) ? 1.0 : 0.0;
+    }
+    S[i * ld + j] = v;
   }
   __syncthreads();
-  for (int j = 0; j < R; ++j) {
-    const double d = P[tri(j, j)];
-    if (!(d > 0.0)) {
-      if (tid == 0) atomicOr(status, kStatusNotSPD);
-      return;                       // uniform: every thread read the same d
-    }
-    const double sd = sqrt(d);
-    __syncthreads();
-    for (int i = j + tid; i < R; i += 256) P[tri(i, j)] = (i == j) ? sd : P[tri(i, j)] / sd;
-    __syncthreads();
-    for (int i = j + 1 + (tid >> 4); i < R; i += 16) {
-      const double lij = P[tri(i, j)];
-      for (int k = j + 1 + (tid & 15); k <= i; k += 16) P[tri(i, k)] -= lij * P[tri(k, j)];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < R * (R + 1) / 2; e += 256) Lg[e] = P[e];
-}
 
-// Sum over the 64 lanes of a wave, butterfly order fixed by lane index.
-__device__ __forceinline__ double wave_sum(double v) {
+  for (int pb = 0; pb < nb; ++pb) {
+    const int p0 = pb * 16;
+    if (wave == 0) {
+      const int ri = lane >> 2, kq = (lane & 3) * 4;
+      for (int jj = 0; jj < 16; ++jj) {
+        const double d = S[(p0 + jj) * ld + p0 + jj];
+        if (!(d > 0.0)) {
+          if (lane == 0) failed = 1;
+          break;                                    // uniform across the wave
+        }
+        const double ljj = sqrt(d);
+        wave_sync();
+        if (lane < 16 && lane >= jj) {
+          double* x = &S[(p0 + lane) * ld + p0 + jj];
+          *x = (lane == jj) ? ljj : *x / ljj;
+        }
+        wave_sync();
+        const double lij = S[(p0 + ri) * ld + p0 + jj];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+        for (int u = 0; u < 4; ++u) {
+          const int k = kq + u;
+          if (k > jj && k <= ri) S[(p0 + ri) * ld + p0 + k] -= lij * S[(p0 + k) * ld + p0 + jj];
+        }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    if (failed) {
+      if (tid == 0) atomicOr(status, kStatusNotSPD);
+      return;                                        // uniform after the barrier
+    }
+    const int base = p0 + 16;
+    if (base >= Rp) break;
+    // Panel rows: L21(i,:) = A21(i,:) L11^{-T}.
+    for (int i = base + tid; i < Rp; i += 256) {
+      double* row = &S[i * ld + p0];
+      double r[16];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) r[jj] = row[jj];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        double v = r[jj];
+#pragma unroll
+        for (int kk = 0; kk < jj; ++kk) v -= r[kk] * S[(p0 + jj) * ld + p0 + kk];
+        r[jj] = v / S[(p0 + jj) * ld + p0 + jj];
+      }
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) row[jj] = r[jj];
+    }
+    __syncthreads();
+    // Trailing lower triangle in 2 x 2 tiles: A22(i,k) -= L21(i,:) . L21(k,:).
+    const int h = base >> 1, hp = Rp >> 1;
+    for (int i2 = h + (tid >> 4); i2 < hp; i2 += 16) {
+      for (int k2 = h + (tid & 15); k2 <= i2; k2 += 16) {
+        const double* a0 = &S[(2 * i2) * ld + p0];
+        const double* a1 = a0 + ld;
+        const double* b0 = &S[(2 * k2) * ld + p0];
+        const double* b1 = b0 + ld;
+        double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+          const double x0 = a0[kk], x1 = a1[kk], y0 = b0[kk], y1 = b1[kk];
+          c00 = fma(x0, y0, c00); c01 = fma(x0, y1, c01);
+          c10 = fma(x1, y0, c10); c11 = fma(x1, y1, c11);
+        }
+        S[(2 * i2) * ld + 2 * k2] -= c00;
+        if (k2 < i2) S[(2 * i2) * ld + 2 * k2 + 1] -= c01;
+        S[(2 * i2 + 1) * ld + 2 * k2] -= c10;
+        S[(2 * i2 + 1) * ld + 2 * k2 + 1] -= c11;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < Rp * Rp; e += 256) {
+    const int i = e / Rp, j = e % Rp;
+    Lg[e] = j <= i ? S[i * ld + j] : 0.0;
+  }
+  for (int i = tid; i < Rp; i += 256) dinv[i] = 1.0 / S[i * ld + i];
 }
 
-// F(q,:) = M(q,:) V^{-1} with V = L L^T: solve y L^T = m (forward with L),
-// then f L = y (back with L^T).  One wave per row; lane owns columns lane and
-// lane + 64.  Skips everything if the Cholesky failed.
-__global__ __launch_bounds__(256) void trsolve_rows_kernel(const float* __restrict__ M, int64_t n, int R,
-                                                           const double* __restrict__ L,
-                                                           const int* __restrict__ status,
-                                                           double* __restrict__ F) {
+// F = M V^{-1} with V = L L^T for 16 rows per workgroup: forward solve
+// G L^T = M, then back solve F L = G, FP64.  L (Rp x Rp) is staged in LDS.
+// Each wave owns 4 rows and each row 16 lanes; rows never interact, so the
+// waves only synchronise within themselves.  Blocked by 16 columns: a
+// 16-step substitution inside the block, then one update of the remaining
+// columns.  Also writes the workgroup's column sums of F^2 (fixed order).
+__global__ __launch_bounds__(256) void trsm_rows_kernel(const float* __restrict__ M, int64_t n, int R,
+                                                        const double* __restrict__ Lg,
+                                                        const double* __restrict__ dinv,
+                                                        const int* __restrict__ status, double* __restrict__ F,
+                                                        double* __restrict__ colsq) {
   if (*status & kStatusNotSPD) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= n) return;
-  double y0 = 0.0, y1 = 0.0;            // y / f of columns lane, lane + 64
-  const float* m = M + q * R;
-  // forward: y_r = (m_r - sum_{s<r} L[r][s] y_s) / L[r][r]
-  for (int r = 0; r < R; ++r) {
-    const double* Lr = L + tri(r, 0);
-    double p = 0.0;
-    if (lane < r) p = Lr[lane] * y0;
-    if (lane + 64 < r) p = fma(Lr[lane + 64], y1, p);
-    const double tot = wave_sum(p);
-    const double yr = ((double)m[r] - tot) / Lr[r];
-    if ((r & 63) == lane) { if (r < 64) y0 = yr; else y1 = yr; }
+  extern __shared__ double lds[];
+  const int Rp = (R + 15) & ~15;
+  const int nb = Rp / 16;
+  const int ldL = Rp + 1, ldY = Rp + 1;
+  double* L = lds;                                   // Rp x ldL
+  double* Y = L + (size_t)Rp * ldL;                  // 16 x ldY
+  double* di = Y + 16 * ldY;                         // Rp
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < Rp * Rp; e += 256) L[(e / Rp) * ldL + (e % Rp)] = Lg[e];
+  for (int e = tid; e < Rp; e += 256) di[e] = dinv[e];
+  const int64_t q0 = (int64_t)blockIdx.x * 16;
+  for (int e = tid; e < 16 * Rp; e += 256) {
+    const int rr = e / Rp, c = e % Rp;
+    const int64_t q = q0 + rr;
+    Y[rr * ldY + c] = (q < n && c < R) ? (double)M[q * R + c] : 0.0;
   }
-  // back: f_r = (y_r - sum_{s>r} L[s][r] f_s) / L[r][r]
-  double f0 = 0.0, f1 = 0.0;
-  for (int r = R - 1; r >= 0; --r) {
-    double p = 0.0;
-    if (lane > r && lane < R) p = L[tri(lane, r)] * f0;
-    if (lane + 64 > r && lane + 64 < R) p = fma(L[tri(lane + 64, r)], f1, p);
-    const double tot = wave_sum(p);
-    const double yr = __shfl(r < 64 ? y0 : y1, r & 63, 64);
-    const double fr = (yr - tot) / L[tri(r, r)];
-    if ((r & 63) == lane) { if (r < 64) f0 = fr; else f1 = fr; }
-  }
-  if (lane < R) F[q * R + lane] = f0;
-  if (lane + 64 < R) F[q * R + lane + 64] = f1;
-}
-
-// part[rb][r] = sum over rows of block rb of F(i,r)^2.
-__global__ __launch_bounds__(256) void colsq_partial_kernel(const double* __restrict__ F, int64_t n, int R,
-                                                            const int* __restrict__ status,
-                                                            double* __restrict__ part) {
-  if (*status & kStatusNotSPD) return;
-  const int c = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int g = threadIdx.x >> 4;       // 16 row groups
-  const int64_t i0 = (int64_t)blockIdx.y * kRowsPerBlock;
-  const int64_t i1 = min(n, i0 + kRowsPerBlock);
-  double acc = 0.0;
-  if (c < R)
-    for (int64_t i = i0 + g; i < i1; i += 16) { const double v = F[i * R + c]; acc = fma(v, v, acc); }
-  __shared__ double sh[16][16];
-  sh[g][threadIdx.x & 15] = acc;
   __syncthreads();
-  if (g == 0 && c < R) {
-    double s = 0.0;
-    for (int q = 0; q < 16; ++q) s += sh[q][threadIdx.x & 15];
-    part[(int64_t)blockIdx.y * R + c] = s;
+  const int row = wave * 4 + (lane >> 4);            // row of this lane inside the block
+  const int c = lane & 15;
+  double* y = Y + row * ldY;
+  // Forward: G(q,r) = (M(q,r) - sum_{s<r} L(r,s) G(q,s)) / L(r,r).
+  for (int b = 0; b < nb; ++b) {
+    const int p0 = b * 16;
+    for (int jj = 0; jj < 16; ++jj) {
+      if (c == jj) y[p0 + jj] *= di[p0 + jj];
+      wave_sync();
+      if (c > jj) y[p0 + c] -= y[p0 + jj] * L[(p0 + c) * ldL + p0 + jj];
+      wave_sync();
+    }
+    for (int t = p0 + 16 + c; t < Rp; t += 16) {
+      double acc = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) acc = fma(y[p0 + jj], L[t * ldL + p0 + jj], acc);
+      y[t] -= acc;
+    }
+    wave_sync();
+  }
+  // Back: F(q,t) = (G(q,t) - sum_{r>t} F(q,r) L(r,t)) / L(t,t).
+  for (int b = nb - 1; b >= 0; --b) {
+    const int p0 = b * 16;
+    for (int jj = 15; jj >= 0; --jj) {
+      if (c == jj) y[p0 + jj] *= di[p0 + jj];
+      wave_sync();
+      if (c < jj) y[p0 + c] -= y[p0 + jj] * L[(p0 + jj) * ldL + p0 + c];
+      wave_sync();
+    }
+    for (int t = c; t < p0; t += 16) {
+      double acc = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) acc = fma(y[p0 + jj], L[(p0 + jj) * ldL + t], acc);
+      y[t] -= acc;
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  for (int e = tid; e < 16 * R; e += 256) {
+    const int rr = e / R, cc = e % R;
+    const int64_t q = q0 + rr;
+    if (q < n) F[q * R + cc] = Y[rr * ldY + cc];
+  }
+  for (int cc = tid; cc < R; cc += 256) {
+    double sacc = 0.0;
+    for (int rr = 0; rr < 16; ++rr) {
+      const double v = (q0 + rr < n) ? Y[rr * ldY + cc] : 0.0;
+      sacc = fma(v, v, sacc);
+    }
+    colsq[(int64_t)blockIdx.x * R + cc] = sacc;
   }
 }
 
-__global__ __launch_bounds__(128) void lambda_kernel(const double* __restrict__ part, int nrb, int R,
-                                                     const int* __restrict__ status, double* __restrict__ lam) {
-  if (*status & kStatusNotSPD) return;
-  const int c = threadIdx.x;
-  if (c >= R) return;
-  double s = 0.0;
-  for (int q = 0; q < nrb; ++q) s += part[(int64_t)q * R + c];
-  lam[c] = sqrt(s);
-}
-
+// lambda_c = sqrt(sum over blocks of colsq) (fixed order, recomputed by every
+// workgroup), factor = F / lambda cast to FP32 (zero columns left unscaled).
 __global__ __launch_bounds__(256) void normalize_kernel(const double* __restrict__ F, int64_t n, int R,
-                                                        const double* __restrict__ lam,
-                                                        const int* __restrict__ status, float* __restrict__ out) {
+                                                        const double* __restrict__ colsq, int nblk,
+                                                        const int* __restrict__ status, double* __restrict__ lam,
+                                                        float* __restrict__ out) {
   if (*status & kStatusNotSPD) return;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n * R) return;
-  const double l = lam[e % R];
-  out[e] = (float)(l > 0.0 ? F[e] / l : F[e]);
+  __shared__ double l[kMaxRank];
+  if (threadIdx.x < R) {
+    double t = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < nblk; ++b) t += colsq[(int64_t)b * R + threadIdx.x];
+    l[threadIdx.x] = sqrt(t);
+    if (blockIdx.x == 0) lam[threadIdx.x] = l[threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t rows = apply_rows(n);
+  const int64_t e0 = (int64_t)blockIdx.x * rows * R;
+  const int64_t e1 = min(n * R, e0 + rows * R);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const double lc = l[e % R];
+    out[e] = (float)(lc > 0.0 ? F[e] / lc : F[e]);
+  }
 }
 
 }  // namespace
 
 size_t solve_ws_bytes(int64_t maxdim, int R) {
-  const int64_t nrb = cdiv(maxdim, kRowsPerBlock);
+  const int64_t nrb = 64;
+  const size_t Rp = (size_t)((R + 15) & ~15);
+  const int64_t md = std::max<int64_t>(maxdim, 1);
   size_t b = 0;
   b += 2 * (size_t)nrb * R * R * sizeof(double);     // Gram partials of the two other factors
-  b += (size_t)R * R * sizeof(double);               // V
-  b += (size_t)R * (R + 1) / 2 * sizeof(double);     // L
-  b += (size_t)maxdim * R * sizeof(double);          // F
-  b += (size_t)nrb * R * sizeof(double);             // column-norm partials
+  b += Rp * Rp * sizeof(double);                      // L
+  b += Rp * sizeof(double);                           // 1 / diag(L)
+  b += (size_t)md * R * sizeof(double);               // F
+  b += (size_t)cdiv(md, 16) * R * sizeof(double);     // column sums of squares per 16 rows
   return b + 6 * 256;
 }
 
@@ -207,32 +322,28 @@ hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3
   const int ob = mode == 2 ? 1 : 2;
   const int64_t n = dims[mode];
   const int tiles_1d = (int)cdiv(R, 16);
-  const int nra = (int)cdiv(dims[oa], kRowsPerBlock);
-  const int nrb = (int)cdiv(dims[ob], kRowsPerBlock);
-  const int nrn = (int)cdiv(n, kRowsPerBlock);
+  const int nra = (int)cdiv(dims[oa], gram_rows(dims[oa]));
+  const int nrb = (int)cdiv(dims[ob], gram_rows(dims[ob]));
+  const int nrb_max = std::max(nra, nrb);
+  const int ntr = (int)cdiv(n, 16);
+  const int nblk = (int)cdiv(n, apply_rows(n));
+  const size_t Rp = (size_t)((R + 15) & ~15);
   char* p = static_cast<char*>(ws);
-  double* pa = reinterpret_cast<double*>(take(p, (size_t)nra * R * R * sizeof(double)));
-  double* pb = reinterpret_cast<double*>(take(p, (size_t)nrb * R * R * sizeof(double)));
-  double* V = reinterpret_cast<double*>(take(p, (size_t)R * R * sizeof(double)));
-  double* L = reinterpret_cast<double*>(take(p, (size_t)R * (R + 1) / 2 * sizeof(double)));
+  double* part = reinterpret_cast<double*>(take(p, 2 * (size_t)nrb_max * R * R * sizeof(double)));
+  double* Lg = reinterpret_cast<double*>(take(p, Rp * Rp * sizeof(double)));
+  double* dinv = reinterpret_cast<double*>(take(p, Rp * sizeof(double)));
   double* F = reinterpret_cast<double*>(take(p, (size_t)n * R * sizeof(double)));
-  double* pn = reinterpret_cast<double*>(take(p, (size_t)nrn * R * sizeof(double)));
+  double* colsq = reinterpret_cast<double*>(take(p, (size_t)ntr * R * sizeof(double)));
 
-  hipLaunchKernelGGL(gram_partial_kernel, dim3(tiles_1d * tiles_1d, nra), dim3(256), 0, st,
-                     factors[oa], dims[oa], R, tiles_1d, pa);
-  hipLaunchKernelGGL(gram_partial_kernel, dim3(tiles_1d * tiles_1d, nrb), dim3(256), 0, st,
-                     factors[ob], dims[ob], R, tiles_1d, pb);
-  hipLaunchKernelGGL(hadamard_kernel, dim3((unsigned)cdiv((int64_t)R * R, 256)), dim3(256), 0, st,
-                     pa, nra, pb, nrb, R, V);
-  const size_t lds = (size_t)R * (R + 1) / 2 * sizeof(double);
-  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(256), lds, st, V, R, L, status);
-  hipLaunchKernelGGL(trsolve_rows_kernel, dim3((unsigned)cdiv(n, 4)), dim3(256), 0, st, M, n, R, L,
-                     status, F);
-  hipLaunchKernelGGL(colsq_partial_kernel, dim3((unsigned)tiles_1d, nrn), dim3(256), 0, st, F, n, R,
-                     status, pn);
-  hipLaunchKernelGGL(lambda_kernel, dim3(1), dim3(128), 0, st, pn, nrn, R, status, lambda);
-  hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)cdiv(n * R, 256)), dim3(256), 0, st, F, n, R,
-                     lambda, status, factor_out);
+  hipLaunchKernelGGL(gram_partial_kernel, dim3(tiles_1d * tiles_1d, nrb_max, 2), dim3(256), 0, st,
+                     factors[oa], dims[oa], factors[ob], dims[ob], R, tiles_1d, nrb_max, part);
+  const size_t lds_chol = Rp * (Rp + 1) * sizeof(double);
+  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(256), lds_chol, st, part, nra, nrb, nrb_max, R, Lg, dinv,
+                     status);
+  const size_t lds_trsm = (Rp * (Rp + 1) + 16 * (Rp + 1) + Rp) * sizeof(double);
+  hipLaunchKernelGGL(trsm_rows_kernel, dim3(ntr), dim3(256), lds_trsm, st, M, n, R, Lg, dinv, status, F, colsq);
+  hipLaunchKernelGGL(normalize_kernel, dim3(nblk), dim3(256), 0, st, F, n, R, colsq, ntr, status, lambda,
+                     factor_out);
   return hipGetLastError();
 }
 
@@ -304,6 +415,7 @@ __global__ __launch_bounds__(256) void fit_final_kernel(const double* __restrict
                                                         double* __restrict__ acc2) {
   __shared__ double sr[256], sn[256];
   double r = 0.0, n = 0.0;
+#pragma unroll 4
   for (int64_t b = threadIdx.x; b < nb; b += 256) { r += part[2 * b]; n += part[2 * b + 1]; }
   sr[threadIdx.x] = r;
   sn[threadIdx.x] = n;

@@ -16,6 +16,7 @@ using mtk::ContractPlan;
 
 struct GraphKey {
   const void* X;
+  const void* Xt;
   int64_t dims[3];
   int fmt;
   const void* slice_exp;
@@ -23,9 +24,9 @@ struct GraphKey {
   const void* lambda;
   int R, prec, with_fit;
   bool operator<(const GraphKey& o) const {
-    return std::tie(X, dims[0], dims[1], dims[2], fmt, slice_exp, f[0], f[1], f[2], lambda, R, prec, with_fit) <
-           std::tie(o.X, o.dims[0], o.dims[1], o.dims[2], o.fmt, o.slice_exp, o.f[0], o.f[1], o.f[2], o.lambda, o.R,
-                    o.prec, o.with_fit);
+    return std::tie(X, Xt, dims[0], dims[1], dims[2], fmt, slice_exp, f[0], f[1], f[2], lambda, R, prec, with_fit) <
+           std::tie(o.X, o.Xt, o.dims[0], o.dims[1], o.dims[2], o.fmt, o.slice_exp, o.f[0], o.f[1], o.f[2], o.lambda,
+                    o.R, o.prec, o.with_fit);
   }
 };
 
@@ -99,9 +100,11 @@ mtk_status check_prec(mtk_ctx* c, const mtk_tensor* X, int prec) {
 }
 
 size_t mttkrp_ws(const int64_t dims[3], int R, int mode, int prec) {
-  ContractPlan p = mtk::make_plan(dims, R, mode, prec, true);
-  ContractPlan q = mtk::make_plan(dims, R, mode, prec, false);
-  return std::max(mtk::contract_ws_bytes(p, prec), mtk::contract_ws_bytes(q, prec));
+  size_t b = 0;
+  for (int tr = 0; tr < 2; ++tr)
+    for (int al = 0; al < 2; ++al)
+      b = std::max(b, mtk::contract_ws_bytes(mtk::make_plan(dims, R, mode, prec, al != 0, tr != 0), prec));
+  return b;
 }
 
 size_t sweep_scratch_bytes(const int64_t dims[3], int R, int prec) {
@@ -201,13 +204,13 @@ mtk_status mtk_reserve(mtk_ctx* c, const int64_t dims[3], int64_t R, int prec) {
   return ensure_ws(c, b, nullptr);
 }
 
-mtk_status mtk_quantize_fp8(mtk_ctx* c, const float* x, const int64_t dims[3], uint8_t* q_out, int32_t* exp_out,
-                            void* stream) {
+mtk_status mtk_quantize_fp8(mtk_ctx* c, const float* x, const int64_t dims[3], uint8_t* q_out, uint8_t* qt_out,
+                            int32_t* exp_out, void* stream) {
   if (!c) return MTK_EINVAL;
   if (!x || !dims || !q_out || !exp_out) return fail(c, MTK_EINVAL, "NULL argument");
   if (!dims_ok(dims)) return fail(c, MTK_EINVAL, "dims out of range");
   HIP_OR_FAIL(c, hipSetDevice(c->device));
-  hipError_t e = mtk::launch_quantize_slices(x, dims[0], dims[1] * dims[2], q_out, exp_out,
+  hipError_t e = mtk::launch_quantize_slices(x, dims[0], dims[1], dims[2], q_out, qt_out, exp_out,
                                              static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(c, e, "quantize");
   return MTK_OK;
@@ -220,8 +223,10 @@ static mtk_status mttkrp_impl(mtk_ctx* c, const mtk_tensor* X, const float* cons
   if (mode == 0) { fr = factors[2]; wt = factors[1]; }
   else if (mode == 1) { fr = factors[2]; wt = factors[0]; }
   else { fr = factors[1]; wt = factors[0]; }
-  ContractPlan p = mtk::make_plan(X->dims, R, mode, prec, aligned16(X->data));
-  hipError_t e = mtk::launch_contract(p, prec, mode, X->data, X->slice_exp, fr, wt, out, ws, st);
+  const bool tr = mode == 2 && X->fmt == MTK_FP8_E4M3 && X->data_t != nullptr;
+  const void* data = tr ? X->data_t : X->data;
+  ContractPlan p = mtk::make_plan(X->dims, R, mode, prec, aligned16(data), tr);
+  hipError_t e = mtk::launch_contract(p, prec, mode, data, X->slice_exp, fr, wt, out, ws, st);
   if (e != hipSuccess) return hip_fail(c, e, "mttkrp launch");
   return MTK_OK;
 }
@@ -328,6 +333,7 @@ mtk_status als_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], d
   const bool with_fit = fit_host != nullptr;
   GraphKey key{};
   key.X = X->data;
+  key.Xt = X->data_t;
   for (int m = 0; m < 3; ++m) { key.dims[m] = X->dims[m]; key.f[m] = factors[m]; }
   key.fmt = X->fmt;
   key.slice_exp = X->slice_exp;

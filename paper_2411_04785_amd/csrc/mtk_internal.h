@@ -24,10 +24,12 @@ struct ContractPlan {
   int nM, nRed, nLoop, R;        // extents: output rows, reduction length, outer loop length
   int64_t sM, sRed, sLoop;       // element strides of X along the three roles
   int nt;                        // MFMA N-tiles (16 columns each) covering R
+  int ncg;                       // column groups: waves of a workgroup splitting R (1 or 2)
+  int ntw;                       // N-tiles per wave = ceil(nt / ncg)
   int nv;                        // reduction values per lane per tile
   int kw;                        // reduction values per wave = 4 * nv
   int wr;                        // waves of a workgroup along the reduction (1, 2 or 4)
-  int mt_per_wg;                 // M-tiles per workgroup = 4 / wr
+  int mt_per_wg;                 // M-tiles per workgroup = 4 / (ncg * wr)
   int n_rg;                      // reduction groups = ceil(nRed / (wr * kw))
   int n_mg;                      // M groups = ceil(ceil(nM / 16) / mt_per_wg)
   int loop_block;                // outer-loop iterations per workgroup
@@ -41,14 +43,17 @@ struct ContractPlan {
 // X_fmt tells how X is stored.  Writes `out` (nM x R FP32) using `ws`
 // (at least contract_ws_bytes) for partial sums and quantised fragments.
 size_t contract_ws_bytes(const ContractPlan& p, int prec);
-ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16);
+// transposed: mode 2 of an FP8 tensor read from its per-slice transposed copy
+// (element (i,j,k) at (i*K + k)*J + j), which makes the reduction over j contiguous.
+ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16,
+                       bool transposed = false);
 hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void* X,
                            const int32_t* slice_exp, const float* frag_src,
                            const float* weight, float* out, void* ws, hipStream_t st);
 
 // FP8 tensor preparation (per mode-1 slice power-of-two scaled e4m3).
-hipError_t launch_quantize_slices(const float* x, int64_t I, int64_t JK, uint8_t* q,
-                                  int32_t* exps, hipStream_t st);
+hipError_t launch_quantize_slices(const float* x, int64_t I, int64_t J, int64_t K, uint8_t* q,
+                                  uint8_t* qt, int32_t* exps, hipStream_t st);
 
 // FP64 Gram / solve pieces.
 size_t solve_ws_bytes(int64_t maxdim, int R);

@@ -32,6 +32,7 @@
 #include "fp8_codec.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace mtk {
 namespace {
@@ -44,13 +45,15 @@ struct KArgs {
   const void* X;
   const int32_t* slice_exp;   // FP8 tensor: per mode-1 slice exponent
   const float* frag_src;      // fragment factor G, nRed x R (FP32 / BF16X3)
-  const uint8_t* frag_q;      // FP8: e4m3 codes of G, nRed x R
+  const uint8_t* frag_q;      // FP8: e4m3 codes of G, column-major R x red_pad, hi then lo plane
+  int red_pad;                // FP8: padded column length of frag_q (covers every window)
   const int32_t* frag_exp;    // FP8: per-column exponent of G
   const float* weight;        // weight factor F, nLoop x R
   float* part;                // slices x nM x R (or the output when slices == 1)
   int64_t sM, sRed, sLoop;
   int nM, nRed, nLoop, R;
   int wr, mt_per_wg, n_rg, n_mg, loop_block, n_lb;
+  int ncg;                    // column groups: waves splitting R over the same tile
   int mode;
 };
 
@@ -72,46 +75,69 @@ template <int NV> struct XRegs<MTK_FP8_E4M3, NV> { uint32_t w[NV / 4]; };
 
 // Load this lane's nv reduction values of tile row `m` (global offset `off`
 // of its first value).  `full` means the whole window and row are in range.
-template <int PREC, int NV, bool CONTIG, bool VEC>
+template <int PREC, int NV, bool CONTIG, bool VEC, bool full>
 __device__ __forceinline__ void load_x(XRegs<PREC, NV>& x, const void* X, int64_t off,
-                                       int64_t sRed, bool row_ok, int red0, int nRed, bool full) {
+                                       int64_t sRed, bool row_ok, int red0, int nRed) {
   if constexpr (PREC == MTK_FP8_E4M3) {
     const uint8_t* p = static_cast<const uint8_t*>(X) + off;
-    if (CONTIG && VEC && full) {
+    if constexpr (CONTIG && VEC && full) {
 #pragma unroll
       for (int q = 0; q < NV / 16; ++q) {
-        uint4 u = *reinterpret_cast<const uint4*>(p + q * 16);
+        const uint4 u = *reinterpret_cast<const uint4*>(p + q * 16);
+        x.w[4 * q + 0] = u.x; x.w[4 * q + 1] = u.y; x.w[4 * q + 2] = u.z; x.w[4 * q + 3] = u.w;
+      }
+    } else if constexpr (CONTIG && VEC) {
+      // nRed is a multiple of 16 here, so each 16-byte chunk is all in or all out.
+#pragma unroll
+      for (int q = 0; q < NV / 16; ++q) {
+        uint4 u = make_uint4(0, 0, 0, 0);
+        if (row_ok && red0 + 16 * q < nRed) u = *reinterpret_cast<const uint4*>(p + q * 16);
         x.w[4 * q + 0] = u.x; x.w[4 * q + 1] = u.y; x.w[4 * q + 2] = u.z; x.w[4 * q + 3] = u.w;
       }
     } else {
+      // Ragged or strided bytes: outside the row or the reduction range the
+      // load reads the tensor's first byte instead and the value is zeroed.
 #pragma unroll
       for (int q = 0; q < NV / 4; ++q) {
         uint32_t w = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          int e = 4 * q + b;
-          uint32_t v = 0;
-          if (row_ok && red0 + e < nRed) v = p[(int64_t)e * sRed];
-          w |= v << (8 * b);
+          const int e = 4 * q + b;
+          const bool ok = full || (row_ok && red0 + e < nRed);
+          const uint32_t v = *(ok ? p + (int64_t)e * sRed : static_cast<const uint8_t*>(X));
+          w |= (ok ? v : 0u) << (8 * b);
         }
         x.w[q] = w;
       }
     }
   } else {
     const float* p = static_cast<const float*>(X) + off;
-    if (CONTIG && VEC && full) {
+    if constexpr (CONTIG && VEC && full) {
 #pragma unroll
       for (int q = 0; q < NV / 4; ++q) {
-        float4 u = *reinterpret_cast<const float4*>(p + q * 4);
+        const float4 u = *reinterpret_cast<const float4*>(p + q * 4);
         x.v[4 * q + 0] = u.x; x.v[4 * q + 1] = u.y; x.v[4 * q + 2] = u.z; x.v[4 * q + 3] = u.w;
       }
-    } else if (full) {
+    } else if constexpr (CONTIG && VEC) {
+      // nRed is a multiple of 4 here, so each 16-byte chunk is all in or all out.
 #pragma unroll
-      for (int e = 0; e < NV; ++e) x.v[e] = p[(int64_t)e * sRed];
+      for (int q = 0; q < NV / 4; ++q) {
+        float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row_ok && red0 + 4 * q < nRed) u = *reinterpret_cast<const float4*>(p + q * 4);
+        x.v[4 * q + 0] = u.x; x.v[4 * q + 1] = u.y; x.v[4 * q + 2] = u.z; x.v[4 * q + 3] = u.w;
+      }
     } else {
+      // Strided or unaligned rows: the address of element e is the lane's
+      // pointer p plus the wave-uniform step e*sRed; outside the row or the
+      // reduction range the load reads the tensor's first element instead
+      // and the value is replaced by zero.
+      const float* X0 = static_cast<const float*>(X);
 #pragma unroll
-      for (int e = 0; e < NV; ++e)
-        x.v[e] = (row_ok && red0 + e < nRed) ? p[(int64_t)e * sRed] : 0.f;
+      for (int e = 0; e < NV; ++e) {
+        const bool ok = full || (row_ok && red0 + e < nRed);
+        const float v = *(ok ? p + (int64_t)e * sRed : X0);
+        x.v[e] = ok ? v : 0.f;
+      }
     }
   }
 }
@@ -139,10 +165,10 @@ template <int NT, int NV> struct Frag<MTK_FP8_E4M3, NT, NV> {
 };
 
 template <int PREC, int NT, int NV>
-__device__ __forceinline__ void load_frag(Frag<PREC, NT, NV>& fr, const KArgs& a, int red0, int n) {
+__device__ __forceinline__ void load_frag(Frag<PREC, NT, NV>& fr, const KArgs& a, int red0, int n, int cb) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int col = t * 16 + n;
+    const int col = cb + t * 16 + n;
     const bool col_ok = col < a.R;
     if constexpr (PREC == MTK_FP32) {
 #pragma unroll
@@ -164,23 +190,22 @@ __device__ __forceinline__ void load_frag(Frag<PREC, NT, NV>& fr, const KArgs& a
         }
       }
     } else {
-      const int64_t plane = (int64_t)a.nRed * a.R;
+      // Codes are column-major, zero-padded to red_pad >= every window end.
+      const int64_t plane = (int64_t)a.R * a.red_pad;
+      const uint8_t* ph = a.frag_q + (int64_t)(col_ok ? col : 0) * a.red_pad + red0;
 #pragma unroll
       for (int s = 0; s < NV / 32; ++s) {
 #pragma unroll
-        for (int w = 0; w < 8; ++w) {
-          uint32_t word = 0, wl = 0;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int red = red0 + s * 32 + w * 4 + b;
-            const bool ok = col_ok && red < a.nRed;
-            const uint32_t v = ok ? a.frag_q[(int64_t)red * a.R + col] : 0u;
-            const uint32_t vl = ok ? a.frag_q[plane + (int64_t)red * a.R + col] : 0u;
-            word |= v << (8 * b);
-            wl |= vl << (8 * b);
+        for (int h = 0; h < 2; ++h) {
+          uint4 u = make_uint4(0, 0, 0, 0), ul = make_uint4(0, 0, 0, 0);
+          if (col_ok) {
+            u = *reinterpret_cast<const uint4*>(ph + s * 32 + h * 16);
+            ul = *reinterpret_cast<const uint4*>(ph + plane + s * 32 + h * 16);
           }
-          fr.q[t][s][w] = static_cast<int>(word);
-          fr.ql[t][s][w] = static_cast<int>(wl);
+          fr.q[t][s][4 * h + 0] = (int)u.x; fr.q[t][s][4 * h + 1] = (int)u.y;
+          fr.q[t][s][4 * h + 2] = (int)u.z; fr.q[t][s][4 * h + 3] = (int)u.w;
+          fr.ql[t][s][4 * h + 0] = (int)ul.x; fr.ql[t][s][4 * h + 1] = (int)ul.y;
+          fr.ql[t][s][4 * h + 2] = (int)ul.z; fr.ql[t][s][4 * h + 3] = (int)ul.w;
         }
       }
       fr.sh[t] = col_ok ? ldexpf(1.f, a.frag_exp[col]) : 0.f;
@@ -260,8 +285,11 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   const int mg = bid % a.n_mg; bid /= a.n_mg;
   const int lb = bid;
 
-  const int wred = wave % a.wr;
-  const int wm = wave / a.wr;
+  // Wave -> (column group, reduction window, M-tile) inside the workgroup.
+  const int cg = wave % a.ncg;
+  const int wred = (wave / a.ncg) % a.wr;
+  const int wm = wave / (a.ncg * a.wr);
+  const int cb = cg * NT * 16;                        // first column of this wave
   const int win = rg * a.wr + wred;                   // reduction window of this wave
   const int red_base = win * KW;
   const int red0 = red_base + g * NV;                 // this lane's first reduction value
@@ -272,7 +300,7 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   const bool tile_full = (m0 + 16 <= a.nM) && (red_base + KW <= a.nRed);
 
   Frag<PREC, NT, NV> fr;
-  load_frag<PREC, NT, NV>(fr, a, red0, m_l);
+  load_frag<PREC, NT, NV>(fr, a, red0, m_l, cb);
 
   f4 acc[NT];
 #pragma unroll
@@ -282,36 +310,58 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   const int l1 = min(a.nLoop, l0 + a.loop_block);
   const int64_t off0 = (int64_t)(row_ok ? row : 0) * a.sM + (int64_t)red0 * a.sRed;
 
+  // The block's weight rows F(l0..l1-1, :) in LDS (FP8 modes 1, 2: times the
+  // slice scale 2^e_i of the loop index), read back with LDS loads so that
+  // the only outstanding global loads in the loop are the X prefetches.
+  extern __shared__ float dyn_lds[];
+  float* wl = dyn_lds;
+  for (int e = threadIdx.x; e < (l1 - l0) * a.R; e += 256) {
+    const int il = e / a.R;
+    float w = a.weight[(int64_t)(l0 + il) * a.R + (e - il * a.R)];
+    if constexpr (PREC == MTK_FP8_E4M3) {
+      if (a.mode != 0) w = ldexpf(w, a.slice_exp[l0 + il]);
+    }
+    wl[e] = w;
+  }
+  __syncthreads();
+
   auto step = [&](const XRegs<PREC, NV>& x, int it) {
     f4 T[NT];
     tile_mfma<PREC, NT, NV>(T, x, fr);
-    float sc = 1.f;
-    if constexpr (PREC == MTK_FP8_E4M3) {
-      if (a.mode != 0) sc = ldexpf(1.f, a.slice_exp[it]);   // slice i = loop index
-    }
+    const float* wr = wl + (it - l0) * a.R;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int col = t * 16 + m_l;
-      const float w = col < a.R ? a.weight[(int64_t)it * a.R + col] * sc : 0.f;
+      const int col = cb + t * 16 + m_l;
+      const float wv = wr[min(col, a.R - 1)];
+      const float w = col < a.R ? wv : 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[t][v] = fmaf(w, T[t][v], acc[t][v]);
     }
   };
 
-  if (l0 < l1) {
+  // Double-buffered stream over the loop block.  Full tiles and ragged tiles
+  // get separate straight-line loops, so the only wait before a tile's
+  // MFMAs is for that tile's own loads (the next tile's stay in flight).
+  // The last prefetch re-reads the final tile instead of branching.
+  auto run = [&](auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    if (l0 >= l1) return;
     XRegs<PREC, NV> xa, xb;
-    load_x<PREC, NV, CONTIG, VEC>(xa, a.X, off0 + (int64_t)l0 * a.sLoop, a.sRed, row_ok, red0, a.nRed, tile_full);
-    for (int it = l0; it < l1; it += 2) {
-      if (it + 1 < l1)
-        load_x<PREC, NV, CONTIG, VEC>(xb, a.X, off0 + (int64_t)(it + 1) * a.sLoop, a.sRed, row_ok, red0, a.nRed, tile_full);
+    load_x<PREC, NV, CONTIG, VEC, FULL>(xa, a.X, off0 + (int64_t)l0 * a.sLoop, a.sRed, row_ok, red0, a.nRed);
+    int it = l0;
+    for (; it + 1 < l1; it += 2) {
+      load_x<PREC, NV, CONTIG, VEC, FULL>(xb, a.X, off0 + (int64_t)(it + 1) * a.sLoop, a.sRed, row_ok, red0, a.nRed);
+      __builtin_amdgcn_sched_barrier(0);        // keep the prefetch ahead of this tile's MFMAs
       step(xa, it);
-      if (it + 1 < l1) {
-        if (it + 2 < l1)
-          load_x<PREC, NV, CONTIG, VEC>(xa, a.X, off0 + (int64_t)(it + 2) * a.sLoop, a.sRed, row_ok, red0, a.nRed, tile_full);
-        step(xb, it + 1);
-      }
+      const int nx = min(it + 2, l1 - 1);
+      load_x<PREC, NV, CONTIG, VEC, FULL>(xa, a.X, off0 + (int64_t)nx * a.sLoop, a.sRed, row_ok, red0, a.nRed);
+      __builtin_amdgcn_sched_barrier(0);
+      step(xb, it + 1);
     }
-  }
+    if (it < l1) step(xa, it);
+  };
+  if (tile_full) run(std::true_type{});
+  else run(std::false_type{});
 
   // FP8 mode 0: each output row is a slice i; apply its power-of-two scale.
   if constexpr (PREC == MTK_FP8_E4M3) {
@@ -328,20 +378,21 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
 
   // Sum the waves that share an M-tile (adjacent reduction windows) in LDS,
   // in fixed wave order, then write this workgroup's partial slice.
-  __shared__ float red_lds[4][NT * 4][64];
   if (a.wr > 1) {
+    float* red_lds = dyn_lds + a.loop_block * a.R;   // [4 waves][NT*4][64]
+    auto at = [&](int w, int k) -> float& { return red_lds[(w * NT * 4 + k) * 64 + lane]; };
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red_lds[wave][t * 4 + v][lane] = acc[t][v];
+      for (int v = 0; v < 4; ++v) at(wave, t * 4 + v) = acc[t][v];
     __syncthreads();
     if (wred != 0) return;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        float s = red_lds[wave][t * 4 + v][lane];
-        for (int q = 1; q < a.wr; ++q) s += red_lds[wave + q][t * 4 + v][lane];
+        float s = at(wave, t * 4 + v);
+        for (int q = 1; q < a.wr; ++q) s += at(wave + q * a.ncg, t * 4 + v);
         acc[t][v] = s;
       }
   }
@@ -350,7 +401,7 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   float* outp = a.part + (int64_t)slice * a.nM * a.R;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int col = t * 16 + m_l;
+    const int col = cb + t * 16 + m_l;
     if (col >= a.R) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -360,24 +411,31 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   }
 }
 
-// out[e] = sum over slices s = 0..S-1 (in this order) of part[s][e].
+// out[e] = sum over the S partial slices of part[s][e].  A block covers 32
+// consecutive elements with 8 slice groups: group q sums slices q, q+8, ...
+// in increasing order, then the 8 group sums are added in group order.  The
+// order depends only on S, so the result is deterministic.
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int S,
                                                             int64_t n, float* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  float s = part[e];
-  for (int q = 1; q < S; ++q) s += part[(int64_t)q * n + e];
-  out[e] = s;
+  __shared__ float red[8][33];
+  const int eo = threadIdx.x & 31;
+  const int q = threadIdx.x >> 5;
+  const int64_t e = (int64_t)blockIdx.x * 32 + eo;
+  float s = 0.f;
+  if (e < n) {
+#pragma unroll 4
+    for (int k = q; k < S; k += 8) s += part[(int64_t)k * n + e];
+  }
+  red[q][eo] = s;
+  __syncthreads();
+  if (q == 0 && e < n) {
+    float t = red[0][eo];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) t += red[k][eo];
+    out[e] = t;
+  }
 }
 
-// ---------------------------------------------------------------------------
-// FP8 fragment preparation, per column r of G (nRed x R):
-//   eh_r = min{e : amax|G(:,r)| <= 448 * 2^e},  hi = e4m3(G(:,r) * 2^-eh_r)
-//   res  = G(:,r) - decode(hi) * 2^eh_r            (exact in binary32)
-//   el_r = min{e : amax|res| <= 448 * 2^e},     lo = e4m3(res * 2^-el_r)
-// Codes: q[0 .. nRed*R) = hi, q[nRed*R .. 2*nRed*R) = lo; ex[r] = eh_r,
-// ex[R + r] = el_r.
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ float e4m3_decode_dev(uint32_t c) {
   const uint32_t e = (c >> 3) & 15u, m = c & 7u;
   const float v = e == 0 ? ldexpf((float)m, -9) : ldexpf(1.f + (float)m * 0.125f, (int)e - 7);
@@ -396,28 +454,36 @@ __device__ float block_max(float m, float* smax) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void frag_quant_kernel(const float* __restrict__ G, int nRed, int R,
+__global__ __launch_bounds__(256) void frag_quant_kernel(const float* __restrict__ G, int nRed, int R, int red_pad,
                                                          uint8_t* __restrict__ q, int32_t* __restrict__ ex) {
   const int r = blockIdx.x;
   __shared__ float smax[256];
-  const int64_t plane = (int64_t)nRed * R;
+  const int64_t plane = (int64_t)R * red_pad;
+  uint8_t* qh = q + (int64_t)r * red_pad;
+  uint8_t* ql = qh + plane;
   float m = 0.f;
   for (int i = threadIdx.x; i < nRed; i += 256) m = fmaxf(m, fabsf(G[(int64_t)i * R + r]));
   const int eh = scale_exponent_dev(block_max(m, smax));
   const float ih = ldexpf(1.f, -eh), sh = ldexpf(1.f, eh);
   float mr = 0.f;
-  for (int i = threadIdx.x; i < nRed; i += 256) {
-    const float g = G[(int64_t)i * R + r];
-    const uint32_t c = e4m3_encode_dev(g * ih);
-    q[(int64_t)i * R + r] = static_cast<uint8_t>(c);
-    mr = fmaxf(mr, fabsf(g - e4m3_decode_dev(c) * sh));
+  for (int i = threadIdx.x; i < red_pad; i += 256) {
+    uint32_t c = 0;
+    if (i < nRed) {
+      const float g = G[(int64_t)i * R + r];
+      c = e4m3_encode_dev(g * ih);
+      mr = fmaxf(mr, fabsf(g - e4m3_decode_dev(c) * sh));
+    }
+    qh[i] = static_cast<uint8_t>(c);
   }
   const int el = scale_exponent_dev(block_max(mr, smax));
   const float il = ldexpf(1.f, -el);
-  for (int i = threadIdx.x; i < nRed; i += 256) {
-    const float g = G[(int64_t)i * R + r];
-    const float res = g - e4m3_decode_dev(q[(int64_t)i * R + r]) * sh;
-    q[plane + (int64_t)i * R + r] = static_cast<uint8_t>(e4m3_encode_dev(res * il));
+  for (int i = threadIdx.x; i < red_pad; i += 256) {
+    uint32_t c = 0;
+    if (i < nRed) {
+      const float g = G[(int64_t)i * R + r];
+      c = e4m3_encode_dev((g - e4m3_decode_dev(qh[i]) * sh) * il);
+    }
+    ql[i] = static_cast<uint8_t>(c);
   }
   if (threadIdx.x == 0) {
     ex[r] = eh;
@@ -427,7 +493,8 @@ __global__ __launch_bounds__(256) void frag_quant_kernel(const float* __restrict
 
 template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
 hipError_t launch_one(const KArgs& a, int64_t grid, hipStream_t st) {
-  hipLaunchKernelGGL((contract_kernel<PREC, NT, NV, CONTIG, VEC>), dim3((unsigned)grid), dim3(256), 0, st, a);
+  const size_t lds = ((size_t)a.loop_block * a.R + (a.wr > 1 ? 4 * NT * 4 * 64 : 0)) * sizeof(float);
+  hipLaunchKernelGGL((contract_kernel<PREC, NT, NV, CONTIG, VEC>), dim3((unsigned)grid), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
@@ -446,8 +513,8 @@ hipError_t dispatch_nv(const KArgs& a, const ContractPlan& p, hipStream_t st) {
   if constexpr (PREC == MTK_FP8_E4M3) {
     switch (p.nv) {
       case 32: return dispatch_cv<PREC, NT, 32>(a, p, st);
-      case 64: if constexpr (NT <= 4) return dispatch_cv<PREC, NT, 64>(a, p, st); break;
-      case 128: if constexpr (NT <= 2) return dispatch_cv<PREC, NT, 128>(a, p, st); break;
+      case 64: if constexpr (NT <= 2) return dispatch_cv<PREC, NT, 64>(a, p, st); break;
+      case 128: if constexpr (NT <= 1) return dispatch_cv<PREC, NT, 128>(a, p, st); break;
     }
   } else {
     switch (p.nv) {
@@ -462,7 +529,16 @@ hipError_t dispatch_nv(const KArgs& a, const ContractPlan& p, hipStream_t st) {
 
 template <int PREC>
 hipError_t dispatch_nt(const KArgs& a, const ContractPlan& p, hipStream_t st) {
-  switch (p.nt) {
+  if constexpr (PREC == MTK_FP8_E4M3) {
+    switch (p.ntw) {
+      case 1: return dispatch_nv<PREC, 1>(a, p, st);
+      case 2: return dispatch_nv<PREC, 2>(a, p, st);
+      case 3: return dispatch_nv<PREC, 3>(a, p, st);
+      case 4: return dispatch_nv<PREC, 4>(a, p, st);
+    }
+    return hipErrorInvalidValue;
+  } else {
+  switch (p.ntw) {
     case 1: return dispatch_nv<PREC, 1>(a, p, st);
     case 2: return dispatch_nv<PREC, 2>(a, p, st);
     case 3: return dispatch_nv<PREC, 3>(a, p, st);
@@ -473,54 +549,67 @@ hipError_t dispatch_nt(const KArgs& a, const ContractPlan& p, hipStream_t st) {
     case 8: return dispatch_nv<PREC, 8>(a, p, st);
   }
   return hipErrorInvalidValue;
+  }
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Column length of the padded FP8 fragment codes: every window of the plan.
+inline int frag_red_pad(const ContractPlan& p) { return p.n_rg * p.wr * p.kw; }
+
 }  // namespace
 
-ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16) {
+ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16, bool transposed) {
   ContractPlan p{};
   const int64_t I = dims[0], J = dims[1], K = dims[2];
   p.R = R;
   p.nt = (int)cdiv(R, 16);
+  // FP8 needs 32 reduction values per lane per MFMA; above 64 columns two
+  // waves split R over the same X tile so the fragments stay in registers.
+  p.ncg = (prec == MTK_FP8_E4M3 && p.nt > 4) ? 2 : 1;
+  p.ntw = (int)cdiv(p.nt, p.ncg);
   if (mode == 0) { p.nM = (int)I; p.nRed = (int)K; p.nLoop = (int)J; p.sM = J * K; p.sRed = 1; p.sLoop = K; }
   else if (mode == 1) { p.nM = (int)J; p.nRed = (int)K; p.nLoop = (int)I; p.sM = K; p.sRed = 1; p.sLoop = J * K; }
+  else if (transposed) { p.nM = (int)K; p.nRed = (int)J; p.nLoop = (int)I; p.sM = J; p.sRed = 1; p.sLoop = J * K; }
   else { p.nM = (int)K; p.nRed = (int)J; p.nLoop = (int)I; p.sM = 1; p.sRed = K; p.sLoop = J * K; }
 
   // Fragment registers per lane: nt*nv (FP32, BF16X3 hi+lo) or nt*nv/4 (FP8); keep <= 64.
   int nv;
   if (prec == MTK_FP8_E4M3) {
     nv = 128;
-    while (nv > 32 && p.nt * nv / 4 > 64) nv /= 2;
+    while (nv > 32 && p.ntw * nv / 2 > 64) nv /= 2;      // hi + lo terms
     while (nv > 32 && 4 * (nv / 2) >= p.nRed) nv /= 2;
   } else {
     nv = 64;
-    while (nv > 8 && p.nt * nv > 64) nv /= 2;
+    while (nv > 8 && p.ntw * nv > 64) nv /= 2;
     while (nv > 8 && 4 * (nv / 2) >= p.nRed) nv /= 2;
   }
   p.nv = nv;
   p.kw = 4 * nv;
   const int64_t windows = cdiv(p.nRed, p.kw);
+  const int wmax = 4 / p.ncg;
   if (p.sRed == 1) {
     p.wr = windows >= 4 ? 4 : (windows >= 2 ? 2 : 1);
+    p.wr = std::min(p.wr, wmax);
   } else {
     p.wr = 1;
   }
-  p.mt_per_wg = 4 / p.wr;
+  p.mt_per_wg = 4 / (p.ncg * p.wr);
   p.n_rg = (int)cdiv(p.nRed, (int64_t)p.wr * p.kw);
   p.n_mg = (int)cdiv(cdiv(p.nM, 16), p.mt_per_wg);
 
-  // Spread the outer loop over enough workgroups to fill 256 CUs several
-  // times, but keep the partial slices' traffic at a few percent of X.
+  // Spread the outer loop over enough workgroups to fill the 256 CUs (two
+  // resident per CU), long enough to amortise each workgroup's fragment load,
+  // and keep the partial slices' traffic at a few percent of X.
   const int64_t base = (int64_t)p.n_rg * p.n_mg;
-  const int64_t target = 2048;
+  const int64_t target = 512;            // two resident workgroups per CU
   int64_t n_lb = std::max<int64_t>(1, std::min<int64_t>(p.nLoop, cdiv(target, base)));
   const double xbytes = (double)I * J * K * (prec == MTK_FP8_E4M3 ? 1.0 : 4.0);
   const double slice_bytes = (double)p.nM * R * 4.0 * 2.0;
   const double cap = std::max(0.03 * xbytes, 4.0 * 1024 * 1024);
   while (n_lb > 1 && (double)p.n_rg * n_lb * slice_bytes > cap) n_lb = cdiv(n_lb, 2);
   p.loop_block = (int)cdiv(p.nLoop, n_lb);
+  p.loop_block = std::min(p.loop_block, std::max(1, 8192 / R));   // staged weights <= 32 KiB
   p.n_lb = (int)cdiv(p.nLoop, p.loop_block);
   p.slices = p.n_rg * p.n_lb;
   const int elem = prec == MTK_FP8_E4M3 ? 1 : 4;
@@ -533,7 +622,7 @@ size_t contract_ws_bytes(const ContractPlan& p, int prec) {
   if (p.slices > 1) b += (size_t)p.slices * p.nM * p.R * sizeof(float);
   b = (b + 255) & ~(size_t)255;
   if (prec == MTK_FP8_E4M3) {
-    b += (2 * (size_t)p.nRed * p.R + 255) & ~(size_t)255;
+    b += (2 * (size_t)frag_red_pad(p) * p.R + 255) & ~(size_t)255;
     b += 256 + 2 * (size_t)p.R * sizeof(int32_t);
   }
   return b;
@@ -551,6 +640,7 @@ hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void
   a.nM = p.nM; a.nRed = p.nRed; a.nLoop = p.nLoop; a.R = p.R;
   a.wr = p.wr; a.mt_per_wg = p.mt_per_wg; a.n_rg = p.n_rg; a.n_mg = p.n_mg;
   a.loop_block = p.loop_block; a.n_lb = p.n_lb;
+  a.ncg = p.ncg;
   a.mode = mode;
   char* w = static_cast<char*>(ws);
   size_t partial_bytes = 0;
@@ -561,9 +651,11 @@ hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void
     a.part = out;
   }
   if (prec == MTK_FP8_E4M3) {
+    const int red_pad = frag_red_pad(p);
     uint8_t* q = reinterpret_cast<uint8_t*>(w + partial_bytes);
-    int32_t* ex = reinterpret_cast<int32_t*>(w + partial_bytes + ((2 * (size_t)p.nRed * p.R + 255) & ~(size_t)255));
-    hipLaunchKernelGGL(frag_quant_kernel, dim3(p.R), dim3(256), 0, st, frag_src, p.nRed, p.R, q, ex);
+    int32_t* ex = reinterpret_cast<int32_t*>(w + partial_bytes + ((2 * (size_t)red_pad * p.R + 255) & ~(size_t)255));
+    hipLaunchKernelGGL(frag_quant_kernel, dim3(p.R), dim3(256), 0, st, frag_src, p.nRed, p.R, red_pad, q, ex);
+    a.red_pad = red_pad;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     a.frag_q = q;
@@ -579,7 +671,7 @@ hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void
   if (e != hipSuccess) return e;
   if (p.slices > 1) {
     const int64_t n = (int64_t)p.nM * p.R;
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(n, 32)), dim3(256), 0, st,
                        a.part, p.slices, n, out);
     e = hipGetLastError();
   }

@@ -42,8 +42,8 @@ class NotSPDError(MtkError):
 
 
 class Tensor(ctypes.Structure):
-    _fields_ = [("data", ctypes.c_void_p), ("dims", ctypes.c_int64 * 3), ("fmt", ctypes.c_int32),
-                ("slice_exp", ctypes.c_void_p)]
+    _fields_ = [("data", ctypes.c_void_p), ("data_t", ctypes.c_void_p), ("dims", ctypes.c_int64 * 3),
+                ("fmt", ctypes.c_int32), ("slice_exp", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -71,7 +71,7 @@ def lib() -> ctypes.CDLL:
         "mtk_last_error": (ctypes.c_char_p, [vp]),
         "mtk_check": (i32, [vp, vp]),
         "mtk_reserve": (i32, [vp, ctypes.POINTER(i64), i64, i32]),
-        "mtk_quantize_fp8": (i32, [vp, vp, ctypes.POINTER(i64), vp, vp, vp]),
+        "mtk_quantize_fp8": (i32, [vp, vp, ctypes.POINTER(i64), vp, vp, vp, vp]),
         "mttkrp": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "gram_solve": (i32, [vp, P3, ctypes.POINTER(i64), i64, i32, vp, vp, vp, vp]),
         "mtk_fit": (i32, [vp, ctypes.POINTER(Tensor), P3, vp, i64, ctypes.POINTER(d), vp]),
@@ -157,29 +157,33 @@ class Context:
     def reserve(self, dims, R, prec):
         self._chk(self._L.mtk_reserve(self.h, _dims(dims), int(R), _prec(prec)))
 
-    def quantize_fp8(self, x, q_out=None, exp_out=None, stream=None):
-        """x: CUDA float32 (I,J,K).  Returns (codes uint8, exponents int32)."""
+    def quantize_fp8(self, x, q_out=None, exp_out=None, transposed=False, stream=None):
+        """x: CUDA float32 (I,J,K).  Returns (codes uint8, exponents int32), or
+        (codes, exponents, slice-transposed codes) with ``transposed=True``."""
         import torch
         if q_out is None:
             q_out = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
         if exp_out is None:
             exp_out = torch.empty(x.shape[0], dtype=torch.int32, device=x.device)
-        self._chk(self._L.mtk_quantize_fp8(self.h, _ptr(x), _dims(x.shape), _ptr(q_out), _ptr(exp_out),
+        qt = None
+        if transposed:
+            qt = torch.empty((x.shape[0], x.shape[2], x.shape[1]), dtype=torch.uint8, device=x.device)
+        self._chk(self._L.mtk_quantize_fp8(self.h, _ptr(x), _dims(x.shape), _ptr(q_out), _ptr(qt), _ptr(exp_out),
                                            _stream(stream)))
-        return q_out, exp_out
+        return (q_out, exp_out, qt) if transposed else (q_out, exp_out)
 
     @staticmethod
-    def tensor_desc(X, slice_exp=None, dims=None) -> Tensor:
+    def tensor_desc(X, slice_exp=None, dims=None, X_t=None) -> Tensor:
         import torch
         fmt = FP8_E4M3 if X.dtype == torch.uint8 else FP32
         d = dims if dims is not None else X.shape
-        return Tensor(_ptr(X), _dims(d), fmt, _ptr(slice_exp))
+        return Tensor(_ptr(X), _ptr(X_t), _dims(d), fmt, _ptr(slice_exp))
 
     def mttkrp(self, X, factors, mode: int, prec="fp32", out=None, slice_exp=None, R=None, stream=None,
-               desc: Optional[Tensor] = None):
+               desc: Optional[Tensor] = None, X_t=None):
         import torch
         R = int(R if R is not None else next(f for f in factors if f is not None).shape[1])
-        d = desc or self.tensor_desc(X, slice_exp)
+        d = desc or self.tensor_desc(X, slice_exp, X_t=X_t)
         if out is None:
             rows = d.dims[mode] if 0 <= int(mode) < 3 else 1     # invalid modes are rejected by the library
             out = torch.empty((rows, R), dtype=torch.float32, device=X.device)
@@ -200,8 +204,8 @@ class Context:
                                      _ptr(lambda_out), _stream(stream)))
         return factor_out, lambda_out
 
-    def fit(self, X, factors, lam, slice_exp=None, stream=None) -> float:
-        d = self.tensor_desc(X, slice_exp)
+    def fit(self, X, factors, lam, slice_exp=None, stream=None, X_t=None) -> float:
+        d = self.tensor_desc(X, slice_exp, X_t=X_t)
         fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
         out = ctypes.c_double()
         self._chk(self._L.mtk_fit(self.h, ctypes.byref(d), fp, _ptr(lam), int(factors[0].shape[1]),
@@ -209,10 +213,10 @@ class Context:
         return out.value
 
     def als_sweep(self, X, factors, lam, nsweeps: int, prec="fp32", slice_exp=None, with_fit=False,
-                  stream=None):
+                  stream=None, X_t=None):
         """In-place CP-ALS sweeps on device factors (FP32) and lambda (FP64).
         Returns the per-sweep fits (numpy) if with_fit else None."""
-        d = self.tensor_desc(X, slice_exp)
+        d = self.tensor_desc(X, slice_exp, X_t=X_t)
         fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
         fits = np.zeros(max(1, nsweeps)) if with_fit else None
         fptr = fits.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if with_fit else None

@@ -144,12 +144,18 @@ def test_fp8_mttkrp(ctx, dims, R):
     from gpu_util import dev, host, rel
     X, facs = _sliced_case(dims, R, seed=11)
     Xd = dev(X)
-    q, e = ctx.quantize_fp8(Xd)
+    q, e, qt = ctx.quantize_fp8(Xd, transposed=True)
     qo, eo = oracle.quantize_slices_e4m3(X)
+    assert np.array_equal(host(qt), np.ascontiguousarray(np.transpose(qo, (0, 2, 1))))
     Xq = oracle.dequantize_slices_e4m3(qo, eo)
+    fd = [dev(f) for f in facs]
     for mode in range(3):
         _say("fp8", dims, R, mode)
-        got = host(ctx.mttkrp(q, [dev(f) for f in facs], mode, "fp8", slice_exp=e))
+        got = host(ctx.mttkrp(q, fd, mode, "fp8", slice_exp=e, X_t=qt))
+        if mode == 2:
+            # The strided path (no transposed copy) must give the same bits.
+            plain = host(ctx.mttkrp(q, fd, mode, "fp8", slice_exp=e))
+            assert np.array_equal(plain, got)
         ref = oracle.mttkrp(X, facs, mode)
         assert rel(got, ref) <= 3e-2
         # Against the dequantised tensor only the factor's two-term e4m3
