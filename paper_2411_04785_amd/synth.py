@@ -185,3 +185,41 @@ def make_requests(n: int = 2000, rate_per_s: float = 200.0, dim_lo: int = 32,
         wl = Workload(f"req{q}", d, R, R, noise_var, seed + 1000 * (q + 1))
         out.append(Request(q, float(t[q]), d, R, sweeps, wl))
     return out
+
+
+# --------------------------------------------------------------------------
+# Fast per-request tensors for the serving benchmark
+# --------------------------------------------------------------------------
+
+class NoisePool:
+    """A fixed, seeded pool of iid N(0,1) FP32 values.  A request takes a
+    window at a seeded offset, so its noise is iid within the request while
+    building it costs a copy instead of fresh Gaussian draws."""
+
+    def __init__(self, n: int = 1 << 26, seed: int = BASE_SEED + 900):
+        self.values = rng(seed, 0).standard_normal(n, dtype=np.float32)
+
+    def window(self, count: int, seed: int) -> np.ndarray:
+        if count > self.values.size:
+            raise ValueError("request larger than the noise pool")
+        off = int(rng(seed, 7).integers(0, self.values.size - count + 1))
+        return self.values[off:off + count]
+
+
+def request_tensor(req: Request, pool: NoisePool):
+    """(X fp32, initial factors fp32) of a serving request: an exact rank-R CP
+    model (FP32 products of N(0,1) factors) plus sqrt(noise_var) times a
+    window of the noise pool."""
+    w = req.workload
+    I, J, K = w.dims
+    g = rng(w.seed, STREAM_FACTORS)
+    A = g.standard_normal((I, w.rank_true), dtype=np.float32)
+    B = g.standard_normal((J, w.rank_true), dtype=np.float32)
+    C = g.standard_normal((K, w.rank_true), dtype=np.float32)
+    # X(i,j,k) = sum_r A(i,r) B(j,r) C(k,r), built as A times the stacked
+    # outer-product rows (input synthesis only; FP32).
+    BC = (B[:, None, :] * C[None, :, :]).reshape(J * K, w.rank_true)
+    X = (A @ BC.T).reshape(I, J, K)
+    if w.noise_var > 0.0:
+        X += np.float32(math.sqrt(w.noise_var)) * pool.window(X.size, w.seed).reshape(X.shape)
+    return np.ascontiguousarray(X, dtype=np.float32), init_factors(w)
