@@ -72,7 +72,7 @@ __device__ __forceinline__ void wave_sync() {
 //
 // V is padded to Rp = 16*ceil(R/16) with an identity block (whose factor is
 // an identity block).  Blocked right-looking with 16 x 16 blocks: wave 0
-// factors the diagonal block (16 wave-synchronous steps), every thread then
+// factors the diagonal block in registers (16 steps, lane shuffles), every thread then
 // solves whole rows of the panel (L21 = A21 L11^{-T}), and the trailing lower
 // triangle is updated (A22 -= L21 L21^T) in 2 x 2 register tiles.  Every sum
 // runs in a fixed order: the factor is deterministic.
@@ -88,49 +88,81 @@ __global__ __launch_bounds__(256) void cholesky_kernel(const double* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t RR = (int64_t)R * R;
   if (tid == 0) failed = 0;
-  for (int e = tid; e < Rp * Rp; e += 256) {
-    const int i = e / Rp, j = e % Rp;
-    double v;
-    if (i < R && j < R) {
-      double a = 0.0, b = 0.0;
-      const int64_t o = (int64_t)i * R + j;
-      // Unrolled so the loads are in flight together; the adds keep index order.
-#pragma unroll 8
-      for (int q = 0; q < nr0; ++q) a += part[(int64_t)q * RR + o];
-#pragma unroll 8
-      for (int q = 0; q < nr1; ++q) b += part[((int64_t)nrb_max + q) * RR + o];
-      v = a * b;
-    } else {
-      v = (i == j) ? 1.0 : 0.0;
+  // V = (sum of Gram partials of factor a) * (same for factor b), padded.
+  // Entries are gathered 8 per thread at a time with all their loads in
+  // flight together (the adds keep partial-index order).
+  {
+    const int total = Rp * Rp;
+    for (int e0 = tid; e0 < total; e0 += 8 * 256) {
+      double va[8], vb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) { va[u] = 0.0; vb[u] = 0.0; }
+      for (int q = 0; q < nr0; ++q) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * 256;
+          const int i = e / Rp, j = e - i * Rp;
+          if (e < total && i < R && j < R) va[u] += part[(int64_t)q * RR + (int64_t)i * R + j];
+        }
+      }
+      for (int q = 0; q < nr1; ++q) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * 256;
+          const int i = e / Rp, j = e - i * Rp;
+          if (e < total && i < R && j < R) vb[u] += part[((int64_t)nrb_max + q) * RR + (int64_t)i * R + j];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        if (e < total) {
+          const int i = e / Rp, j = e - i * Rp;
+          S[i * ld + j] = (i < R && j < R) ? va[u] * vb[u] : (i == j ? 1.0 : 0.0);
+        }
+      }
     }
-    S[i * ld + j] = v;
   }
   __syncthreads();
 
   for (int pb = 0; pb < nb; ++pb) {
     const int p0 = pb * 16;
     if (wave == 0) {
+      // Diagonal block in registers: lane l holds row ri = l/4, columns
+      // kq..kq+3 (kq = 4*(l%4)).  Step jj broadcasts the pivot with a
+      // readlane, the row's L(ri,jj) within its quad, and L(k,jj) of the
+      // lane's four columns with lane shuffles; no LDS round trips.
       const int ri = lane >> 2, kq = (lane & 3) * 4;
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = S[(p0 + ri) * ld + p0 + kq + u];
+      bool bad = false;
+#pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
-        const double d = S[(p0 + jj) * ld + p0 + jj];
-        if (!(d > 0.0)) {
-          if (lane == 0) failed = 1;
-          break;                                    // uniform across the wave
-        }
+        const int own = jj * 4 + (jj >> 2);              // lane holding (jj, jj)
+        const double d = __shfl(a[jj & 3], own, 64);
+        if (!(d > 0.0)) { bad = true; break; }           // uniform across the wave
         const double ljj = sqrt(d);
-        wave_sync();
-        if (lane < 16 && lane >= jj) {
-          double* x = &S[(p0 + lane) * ld + p0 + jj];
-          *x = (lane == jj) ? ljj : *x / ljj;
+        const double inv = 1.0 / ljj;
+        if ((lane & 3) == (jj >> 2)) {                    // lanes holding column jj
+          if (ri == jj) a[jj & 3] = ljj;
+          else if (ri > jj) a[jj & 3] *= inv;
         }
-        wave_sync();
-        const double lij = S[(p0 + ri) * ld + p0 + jj];
+        const double lij = __shfl(a[jj & 3], (lane & ~3) | (jj >> 2), 64);
+        double lkj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) lkj[u] = __shfl(a[jj & 3], (kq + u) * 4 + (jj >> 2), 64);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int k = kq + u;
-          if (k > jj && k <= ri) S[(p0 + ri) * ld + p0 + k] -= lij * S[(p0 + k) * ld + p0 + jj];
+          if (k > jj && k <= ri) a[u] -= lij * lkj[u];
         }
-        wave_sync();
+      }
+      if (bad) {
+        if (lane == 0) failed = 1;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) S[(p0 + ri) * ld + p0 + kq + u] = a[u];
       }
     }
     __syncthreads();
@@ -315,36 +347,79 @@ static inline char* take(char*& p, size_t bytes) {
   return r;
 }
 
-hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3], int R, int mode,
-                             const float* M, float* factor_out, double* lambda, void* ws, int* status,
-                             hipStream_t st) {
+namespace {
+
+// Workspace carve-up shared by the two halves of the update.
+struct SolveWs {
+  double* part;
+  double* Lg;
+  double* dinv;
+  double* F;
+  double* colsq;
+  int nra, nrb, nrb_max, ntr, nblk;
+};
+
+SolveWs solve_ws(const int64_t dims[3], int R, int mode, void* ws) {
   const int oa = mode == 0 ? 1 : 0;
   const int ob = mode == 2 ? 1 : 2;
   const int64_t n = dims[mode];
-  const int tiles_1d = (int)cdiv(R, 16);
-  const int nra = (int)cdiv(dims[oa], gram_rows(dims[oa]));
-  const int nrb = (int)cdiv(dims[ob], gram_rows(dims[ob]));
-  const int nrb_max = std::max(nra, nrb);
-  const int ntr = (int)cdiv(n, 16);
-  const int nblk = (int)cdiv(n, apply_rows(n));
+  SolveWs w{};
+  w.nra = (int)cdiv(dims[oa], gram_rows(dims[oa]));
+  w.nrb = (int)cdiv(dims[ob], gram_rows(dims[ob]));
+  w.nrb_max = std::max(w.nra, w.nrb);
+  w.ntr = (int)cdiv(n, 16);
+  w.nblk = (int)cdiv(n, apply_rows(n));
   const size_t Rp = (size_t)((R + 15) & ~15);
   char* p = static_cast<char*>(ws);
-  double* part = reinterpret_cast<double*>(take(p, 2 * (size_t)nrb_max * R * R * sizeof(double)));
-  double* Lg = reinterpret_cast<double*>(take(p, Rp * Rp * sizeof(double)));
-  double* dinv = reinterpret_cast<double*>(take(p, Rp * sizeof(double)));
-  double* F = reinterpret_cast<double*>(take(p, (size_t)n * R * sizeof(double)));
-  double* colsq = reinterpret_cast<double*>(take(p, (size_t)ntr * R * sizeof(double)));
+  w.part = reinterpret_cast<double*>(take(p, 2 * (size_t)w.nrb_max * R * R * sizeof(double)));
+  w.Lg = reinterpret_cast<double*>(take(p, Rp * Rp * sizeof(double)));
+  w.dinv = reinterpret_cast<double*>(take(p, Rp * sizeof(double)));
+  w.F = reinterpret_cast<double*>(take(p, (size_t)n * R * sizeof(double)));
+  w.colsq = reinterpret_cast<double*>(take(p, (size_t)w.ntr * R * sizeof(double)));
+  return w;
+}
 
-  hipLaunchKernelGGL(gram_partial_kernel, dim3(tiles_1d * tiles_1d, nrb_max, 2), dim3(256), 0, st,
-                     factors[oa], dims[oa], factors[ob], dims[ob], R, tiles_1d, nrb_max, part);
+}  // namespace
+
+// First half: the Gram matrices of the two other factors and the Cholesky
+// factor of their Hadamard product.  Reads only factors[m], m != mode, so it
+// may run concurrently with the mode's MTTKRP.
+hipError_t launch_gram_chol(const float* const factors[3], const int64_t dims[3], int R, int mode, void* ws,
+                            int* status, hipStream_t st) {
+  const int oa = mode == 0 ? 1 : 0;
+  const int ob = mode == 2 ? 1 : 2;
+  const int tiles_1d = (int)cdiv(R, 16);
+  const size_t Rp = (size_t)((R + 15) & ~15);
+  SolveWs w = solve_ws(dims, R, mode, ws);
+  hipLaunchKernelGGL(gram_partial_kernel, dim3(tiles_1d * tiles_1d, w.nrb_max, 2), dim3(256), 0, st,
+                     factors[oa], dims[oa], factors[ob], dims[ob], R, tiles_1d, w.nrb_max, w.part);
   const size_t lds_chol = Rp * (Rp + 1) * sizeof(double);
-  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(256), lds_chol, st, part, nra, nrb, nrb_max, R, Lg, dinv,
-                     status);
+  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(256), lds_chol, st, w.part, w.nra, w.nrb, w.nrb_max, R, w.Lg,
+                     w.dinv, status);
+  return hipGetLastError();
+}
+
+// Second half: F = M V^{-1} by the two triangular solves, lambda and the
+// normalised FP32 factor.  Needs launch_gram_chol's results in the same ws.
+hipError_t launch_solve_apply(const int64_t dims[3], int R, int mode, const float* M, float* factor_out,
+                              double* lambda, void* ws, int* status, hipStream_t st) {
+  const int64_t n = dims[mode];
+  const size_t Rp = (size_t)((R + 15) & ~15);
+  SolveWs w = solve_ws(dims, R, mode, ws);
   const size_t lds_trsm = (Rp * (Rp + 1) + 16 * (Rp + 1) + Rp) * sizeof(double);
-  hipLaunchKernelGGL(trsm_rows_kernel, dim3(ntr), dim3(256), lds_trsm, st, M, n, R, Lg, dinv, status, F, colsq);
-  hipLaunchKernelGGL(normalize_kernel, dim3(nblk), dim3(256), 0, st, F, n, R, colsq, ntr, status, lambda,
+  hipLaunchKernelGGL(trsm_rows_kernel, dim3(w.ntr), dim3(256), lds_trsm, st, M, n, R, w.Lg, w.dinv, status, w.F,
+                     w.colsq);
+  hipLaunchKernelGGL(normalize_kernel, dim3(w.nblk), dim3(256), 0, st, w.F, n, R, w.colsq, w.ntr, status, lambda,
                      factor_out);
   return hipGetLastError();
+}
+
+hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3], int R, int mode,
+                             const float* M, float* factor_out, double* lambda, void* ws, int* status,
+                             hipStream_t st) {
+  hipError_t e = launch_gram_chol(factors, dims, R, mode, ws, status, st);
+  if (e != hipSuccess) return e;
+  return launch_solve_apply(dims, R, mode, M, factor_out, lambda, ws, status, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -107,13 +107,17 @@ size_t mttkrp_ws(const int64_t dims[3], int R, int mode, int prec) {
   return b;
 }
 
-size_t sweep_scratch_bytes(const int64_t dims[3], int R, int prec) {
+// Scratch of a sweep: [contraction / fit region][solve region]; the two
+// regions are disjoint because Gram + Cholesky overlap the MTTKRP.
+size_t sweep_contract_bytes(const int64_t dims[3], int R, int prec) {
   size_t b = 0;
   for (int m = 0; m < 3; ++m) b = std::max(b, mttkrp_ws(dims, R, m, prec));
+  return round256(std::max(b, mtk::fit_ws_bytes(dims)));
+}
+
+size_t sweep_scratch_bytes(const int64_t dims[3], int R, int prec) {
   const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
-  b = std::max(b, mtk::solve_ws_bytes(maxdim, R));
-  b = std::max(b, mtk::fit_ws_bytes(dims));
-  return b;
+  return sweep_contract_bytes(dims, R, prec) + mtk::solve_ws_bytes(maxdim, R);
 }
 
 }  // namespace
@@ -147,6 +151,14 @@ mtk_status mtk_create(mtk_ctx** ctx, int device) {
     return MTK_EHIP;
   }
   c->graph_cache = gc;
+  bool ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
+  for (int m = 0; m < 3 && ok; ++m)
+    ok = hipEventCreateWithFlags(&c->fork_ev[m], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&c->join_ev[m], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    mtk_destroy(c);
+    return MTK_EHIP;
+  }
   *ctx = c;
   return MTK_OK;
 }
@@ -173,6 +185,11 @@ mtk_status mtk_destroy(mtk_ctx* c) {
     if (gc->capture_stream) (void)hipStreamDestroy(gc->capture_stream);
     delete gc;
   }
+  for (int m = 0; m < 3; ++m) {
+    if (c->fork_ev[m]) (void)hipEventDestroy(c->fork_ev[m]);
+    if (c->join_ev[m]) (void)hipEventDestroy(c->join_ev[m]);
+  }
+  if (c->side) (void)hipStreamDestroy(c->side);
   if (c->ws) (void)hipFree(c->ws);
   if (c->d_status) (void)hipFree(c->d_status);
   if (c->d_fit) (void)hipFree(c->d_fit);
@@ -290,17 +307,26 @@ mtk_status mtk_fit(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3
 
 // One CP-ALS sweep (modes 0, 1, 2) enqueued on `st`, optionally followed by
 // the fit partial sums into c->d_fit.  M buffer and scratch come from ws.
+// Within a mode, Gram + Cholesky of the other two factors run on the side
+// stream while the MTTKRP runs on `st`; the triangular solve waits for both.
 static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int R,
                                 int prec, bool with_fit, hipStream_t st) {
   const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
   float* M = static_cast<float*>(c->ws);
   void* scratch = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
+  void* solve_ws = static_cast<char*>(scratch) + sweep_contract_bytes(X->dims, R, prec);
   const float* cf[3] = {factors[0], factors[1], factors[2]};
   for (int n = 0; n < 3; ++n) {
+    HIP_OR_FAIL(c, hipEventRecord(c->fork_ev[n], st));
+    HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->fork_ev[n], 0));
+    hipError_t e = mtk::launch_gram_chol(cf, X->dims, R, n, solve_ws, c->d_status, c->side);
+    if (e != hipSuccess) return hip_fail(c, e, "gram/cholesky launch");
+    HIP_OR_FAIL(c, hipEventRecord(c->join_ev[n], c->side));
     mtk_status s = mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st);
     if (s != MTK_OK) return s;
-    hipError_t e = mtk::launch_gram_solve(cf, X->dims, R, n, M, factors[n], lambda, scratch, c->d_status, st);
-    if (e != hipSuccess) return hip_fail(c, e, "gram_solve launch");
+    HIP_OR_FAIL(c, hipStreamWaitEvent(st, c->join_ev[n], 0));
+    e = mtk::launch_solve_apply(X->dims, R, n, M, factors[n], lambda, solve_ws, c->d_status, st);
+    if (e != hipSuccess) return hip_fail(c, e, "solve launch");
   }
   if (with_fit) {
     hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, R, c->d_fit, scratch, st);

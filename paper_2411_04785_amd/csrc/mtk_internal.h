@@ -60,6 +60,12 @@ size_t solve_ws_bytes(int64_t maxdim, int R);
 hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3], int R,
                              int mode, const float* M, float* factor_out, double* lambda,
                              void* ws, int* status, hipStream_t st);
+// The same update in two halves: Gram + Cholesky (needs only the other two
+// factors, so it can overlap the mode's MTTKRP), then solve + normalise.
+hipError_t launch_gram_chol(const float* const factors[3], const int64_t dims[3], int R, int mode,
+                            void* ws, int* status, hipStream_t st);
+hipError_t launch_solve_apply(const int64_t dims[3], int R, int mode, const float* M, float* factor_out,
+                              double* lambda, void* ws, int* status, hipStream_t st);
 size_t fit_ws_bytes(const int64_t dims[3]);
 hipError_t launch_fit(const void* X, int fmt, const int32_t* slice_exp, const int64_t dims[3],
                       const float* const factors[3], const double* lambda, int R,
@@ -76,4 +82,7 @@ struct mtk_ctx {
   double* d_fit = nullptr;        // fit accumulators
   std::string last_error;
   void* graph_cache = nullptr;    // als_sweep graph cache (see api.hip)
+  hipStream_t side = nullptr;     // second stream of the captured sweep
+  hipEvent_t fork_ev[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t join_ev[3] = {nullptr, nullptr, nullptr};
 };

@@ -73,6 +73,13 @@ template <int NV> struct XRegs<MTK_FP32, NV> { float v[NV]; };
 template <int NV> struct XRegs<MTK_BF16X3, NV> { float v[NV]; };
 template <int NV> struct XRegs<MTK_FP8_E4M3, NV> { uint32_t w[NV / 4]; };
 
+// Tiles kept in flight per wave: deeper for small tiles so that every CU has
+// enough bytes outstanding to cover the HBM latency.
+template <int PREC, int NV> struct PipeDepth {
+  static constexpr int tile_vgprs = (PREC == MTK_FP8_E4M3) ? NV / 4 : NV;
+  static constexpr int value = tile_vgprs <= 8 ? 4 : (tile_vgprs <= 16 ? 3 : 2);
+};
+
 // Load this lane's nv reduction values of tile row `m` (global offset `off`
 // of its first value).  `full` means the whole window and row are in range.
 template <int PREC, int NV, bool CONTIG, bool VEC, bool full>
@@ -156,12 +163,13 @@ template <int PREC, int NT, int NV> struct Frag;
 template <int NT, int NV> struct Frag<MTK_FP32, NT, NV> { float f[NT][NV]; };
 template <int NT, int NV> struct Frag<MTK_BF16X3, NT, NV> { bf16x8 hi[NT][NV / 8]; bf16x8 lo[NT][NV / 8]; };
 // FP8: the factor is held as two e4m3 terms, hi = e4m3(G 2^-eh) and
-// lo = e4m3((G - hi 2^eh) 2^-el), with per-column exponents eh, el; scl holds
-// 2^eh and 2^el of the lane's column for every N-tile.
+// lo = e4m3((G - hi 2^eh) 2^-el), with per-column exponents eh, el.  The
+// exponents of the lane's column travel as E8M0 B-operand scales (127 + e),
+// which the MFMA applies per column, so both terms accumulate into one tile.
 template <int NT, int NV> struct Frag<MTK_FP8_E4M3, NT, NV> {
   i32x8 q[NT][NV / 32];
   i32x8 ql[NT][NV / 32];
-  float sh[NT], sl[NT];
+  int sh[NT], sl[NT];
 };
 
 template <int PREC, int NT, int NV>
@@ -208,8 +216,8 @@ __device__ __forceinline__ void load_frag(Frag<PREC, NT, NV>& fr, const KArgs& a
           fr.ql[t][s][4 * h + 2] = (int)ul.z; fr.ql[t][s][4 * h + 3] = (int)ul.w;
         }
       }
-      fr.sh[t] = col_ok ? ldexpf(1.f, a.frag_exp[col]) : 0.f;
-      fr.sl[t] = col_ok ? ldexpf(1.f, a.frag_exp[a.R + col]) : 0.f;
+      fr.sh[t] = col_ok ? 127 + a.frag_exp[col] : 127;          // zero codes past R
+      fr.sl[t] = col_ok ? 127 + a.frag_exp[a.R + col] : 127;
     }
   }
 }
@@ -246,27 +254,20 @@ __device__ __forceinline__ void tile_mfma(f4 (&T)[NT], const XRegs<PREC, NV>& x,
       for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.hi[t][s], T[t], 0, 0, 0);
     }
   } else {
-    f4 Tl[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) Tl[t] = zero4();
 #pragma unroll
     for (int s = 0; s < NV / 32; ++s) {
       i32x8 xq;
 #pragma unroll
       for (int w = 0; w < 8; ++w) xq[w] = static_cast<int>(x.w[s * 8 + w]);
-      // e4m3 x e4m3 (format code 0 for both), unit E8M0 scales (127 = 2^0).
+      // e4m3 x e4m3 (format code 0 for both); A scale 2^0 (127), B scale
+      // 2^eh / 2^el of the lane's column.  Small term first.
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        T[t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(xq, fr.q[t][s], T[t], 0, 0, 0, 127, 0, 127);
+        T[t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(xq, fr.ql[t][s], T[t], 0, 0, 0, 127, 0, fr.sl[t]);
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        Tl[t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(xq, fr.ql[t][s], Tl[t], 0, 0, 0, 127, 0, 127);
+        T[t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(xq, fr.q[t][s], T[t], 0, 0, 0, 127, 0, fr.sh[t]);
     }
-    // Back to the factor's units: column scales of the two terms.
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T[t][v] = fmaf(T[t][v], fr.sh[t], Tl[t][v] * fr.sl[t]);
   }
 }
 
@@ -339,26 +340,29 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
     }
   };
 
-  // Double-buffered stream over the loop block.  Full tiles and ragged tiles
-  // get separate straight-line loops, so the only wait before a tile's
-  // MFMAs is for that tile's own loads (the next tile's stay in flight).
-  // The last prefetch re-reads the final tile instead of branching.
+  // Stream over the loop block with DEPTH tiles in flight (registers).  Full
+  // tiles and ragged tiles get separate straight-line loops, so the only
+  // wait before a tile's MFMAs is for that tile's own loads.  Prefetches past
+  // the block re-read its last tile instead of branching.
   auto run = [&](auto full_tag) {
     constexpr bool FULL = decltype(full_tag)::value;
+    constexpr int D = PipeDepth<PREC, NV>::value;
     if (l0 >= l1) return;
-    XRegs<PREC, NV> xa, xb;
-    load_x<PREC, NV, CONTIG, VEC, FULL>(xa, a.X, off0 + (int64_t)l0 * a.sLoop, a.sRed, row_ok, red0, a.nRed);
-    int it = l0;
-    for (; it + 1 < l1; it += 2) {
-      load_x<PREC, NV, CONTIG, VEC, FULL>(xb, a.X, off0 + (int64_t)(it + 1) * a.sLoop, a.sRed, row_ok, red0, a.nRed);
-      __builtin_amdgcn_sched_barrier(0);        // keep the prefetch ahead of this tile's MFMAs
-      step(xa, it);
-      const int nx = min(it + 2, l1 - 1);
-      load_x<PREC, NV, CONTIG, VEC, FULL>(xa, a.X, off0 + (int64_t)nx * a.sLoop, a.sRed, row_ok, red0, a.nRed);
-      __builtin_amdgcn_sched_barrier(0);
-      step(xb, it + 1);
+    XRegs<PREC, NV> x[D];
+#pragma unroll
+    for (int d = 0; d < D - 1; ++d)
+      load_x<PREC, NV, CONTIG, VEC, FULL>(x[d], a.X, off0 + (int64_t)min(l0 + d, l1 - 1) * a.sLoop, a.sRed,
+                                          row_ok, red0, a.nRed);
+    for (int it = l0; it < l1; it += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int nx = min(it + d + D - 1, l1 - 1);
+        load_x<PREC, NV, CONTIG, VEC, FULL>(x[(d + D - 1) % D], a.X, off0 + (int64_t)nx * a.sLoop, a.sRed,
+                                            row_ok, red0, a.nRed);
+        __builtin_amdgcn_sched_barrier(0);      // keep the prefetch ahead of this tile's MFMAs
+        if (it + d < l1) step(x[d], it + d);
+      }
     }
-    if (it < l1) step(xa, it);
   };
   if (tile_full) run(std::true_type{});
   else run(std::false_type{});
