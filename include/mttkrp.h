@@ -133,7 +133,7 @@ mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[
 
 /* Normal-equation update of one factor (FP64 on the device).
  *  V = *_{m != mode} A_m^T A_m  (R x R, FP64, from the FP32 factors)
- *  V = L L^T (Cholesky), V^{-1} = L^{-T} L^{-1}, F = M V^{-1} (FP64)
+ *  V = L L^T (Cholesky), W = L^{-1}, V^{-1} = W^T W, F = M V^{-1} (FP64)
  *  lambda_out[r] = ||F(:,r)||_2 (FP64); factor_out = F(:,r)/lambda_r cast
  *  to FP32 (a column with lambda_r == 0 is written unscaled).
  *  factors    : three device pointers (factors[mode] not read, may be NULL).

@@ -108,7 +108,8 @@ size_t mttkrp_ws(const int64_t dims[3], int R, int mode, int prec) {
 }
 
 // Scratch of a sweep: [contraction / fit region][solve region]; the two
-// regions are disjoint because Gram + Cholesky overlap the MTTKRP.
+// regions are disjoint because the Gram matrices kept in the solve region
+// live across the MTTKRPs.
 size_t sweep_contract_bytes(const int64_t dims[3], int R, int prec) {
   size_t b = 0;
   for (int m = 0; m < 3; ++m) b = std::max(b, mttkrp_ws(dims, R, m, prec));
@@ -133,7 +134,8 @@ mtk_status mtk_create(mtk_ctx** ctx, int device) {
   mtk_ctx* c = new (std::nothrow) mtk_ctx();
   if (!c) return MTK_ENOMEM;
   c->device = device;
-  if (hipMalloc(&c->d_status, 256) != hipSuccess || hipMemset(c->d_status, 0, 256) != hipSuccess) {
+  const size_t status_bytes = mtk::kStatusWords * sizeof(int);
+  if (hipMalloc(&c->d_status, status_bytes) != hipSuccess || hipMemset(c->d_status, 0, status_bytes) != hipSuccess) {
     delete c;
     return MTK_ENOMEM;
   }
@@ -307,26 +309,57 @@ mtk_status mtk_fit(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3
 
 // One CP-ALS sweep (modes 0, 1, 2) enqueued on `st`, optionally followed by
 // the fit partial sums into c->d_fit.  M buffer and scratch come from ws.
-// Within a mode, Gram + Cholesky of the other two factors run on the side
-// stream while the MTTKRP runs on `st`; the triangular solve waits for both.
+// Per mode: MTTKRP, then the update (Cholesky + inverse of V from the Gram
+// matrices kept in the solve region, F = M V^{-1}, normalise, and the Gram
+// matrix of the new factor); for large R the factorisation runs on the
+// side stream concurrently with the MTTKRP.  The Gram matrices of factors 1 and 2 must be
+// in the solve region before the first sweep (enqueue_initial_grams).
+static void* sweep_solve_ws(mtk_ctx* c, const int64_t dims[3], int R, int prec) {
+  const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
+  char* scratch = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
+  return scratch + sweep_contract_bytes(dims, R, prec);
+}
+
+static mtk_status enqueue_initial_grams(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], int R, int prec,
+                                        hipStream_t st) {
+  const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
+  const float* cf[3] = {factors[0], factors[1], factors[2]};
+  hipError_t e = mtk::launch_grams(cf, X->dims, R, 1, 2, maxdim, sweep_solve_ws(c, X->dims, R, prec), c->d_status, st);
+  if (e != hipSuccess) return hip_fail(c, e, "Gram launch");
+  return MTK_OK;
+}
+
+// Smallest R whose factorisation runs on the side stream.  Measured: at
+// R = 32 the one-workgroup factorisation, slowed several-fold by sharing a
+// CU with the contraction, ends after it; from R = 64 on it is hidden.
+constexpr int kOverlapMinRank = 41;
+
 static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int R,
                                 int prec, bool with_fit, hipStream_t st) {
   const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
   float* M = static_cast<float*>(c->ws);
   void* scratch = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
-  void* solve_ws = static_cast<char*>(scratch) + sweep_contract_bytes(X->dims, R, prec);
+  void* solve_ws = sweep_solve_ws(c, X->dims, R, prec);
   const float* cf[3] = {factors[0], factors[1], factors[2]};
+  const bool overlap = R >= kOverlapMinRank;
   for (int n = 0; n < 3; ++n) {
+    if (!overlap) {
+      mtk_status s = mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st);
+      if (s != MTK_OK) return s;
+      hipError_t e = mtk::launch_update(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st);
+      if (e != hipSuccess) return hip_fail(c, e, "update launch");
+      continue;
+    }
     HIP_OR_FAIL(c, hipEventRecord(c->fork_ev[n], st));
     HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->fork_ev[n], 0));
-    hipError_t e = mtk::launch_gram_chol(cf, X->dims, R, n, solve_ws, c->d_status, c->side);
-    if (e != hipSuccess) return hip_fail(c, e, "gram/cholesky launch");
+    hipError_t e = mtk::launch_factor(X->dims, R, n, maxdim, solve_ws, c->d_status, c->side);
+    if (e != hipSuccess) return hip_fail(c, e, "factorisation launch");
     HIP_OR_FAIL(c, hipEventRecord(c->join_ev[n], c->side));
     mtk_status s = mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st);
     if (s != MTK_OK) return s;
     HIP_OR_FAIL(c, hipStreamWaitEvent(st, c->join_ev[n], 0));
-    e = mtk::launch_solve_apply(X->dims, R, n, M, factors[n], lambda, solve_ws, c->d_status, st);
-    if (e != hipSuccess) return hip_fail(c, e, "solve launch");
+    e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st);
+    if (e != hipSuccess) return hip_fail(c, e, "update launch");
   }
   if (with_fit) {
     hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, R, c->d_fit, scratch, st);
@@ -355,8 +388,8 @@ mtk_status als_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], d
   }
   if (nsweeps == 0) return mtk_check(c, stream);
 
-  GraphCache* gc = static_cast<GraphCache*>(c->graph_cache);
   const bool with_fit = fit_host != nullptr;
+  GraphCache* gc = static_cast<GraphCache*>(c->graph_cache);
   GraphKey key{};
   key.X = X->data;
   key.Xt = X->data_t;
@@ -389,6 +422,9 @@ mtk_status als_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], d
     gc->graphs.push_back(g);
     gc->execs[key] = exec;
   }
+  // The Gram matrices the first mode needs; every later one is formed by the
+  // update that writes its factor.
+  if ((s = enqueue_initial_grams(c, X, factors, (int)R, prec, st)) != MTK_OK) return s;
   std::vector<double> acc(with_fit ? 2 * (size_t)nsweeps : 0);
   for (int sw = 0; sw < nsweeps; ++sw) {
     HIP_OR_FAIL(c, hipGraphLaunch(exec, st));

@@ -19,6 +19,22 @@ constexpr int kWave = 64;
 // Device-side sticky status bits (OR-ed into the context's status word).
 constexpr int kStatusNotSPD = 1;
 
+// Gram partials are stored per factor as [tile pair][row block][16 x 16],
+// with room for this many row blocks.
+constexpr int kGramBlocksMax = 16;
+
+// Inputs / outputs of the FP64 factorisation of one update's V (see
+// factor_device.h): V^{-1} from the Gram partials of the two other factors.
+struct FactorArgs {
+  const double* pa;   // Gram partials of the first other factor
+  int na;             // its row blocks
+  const double* pb;   // Gram partials of the second other factor
+  int nb;
+  int R;
+  double* vinv;       // out: V^{-1}, R x R row-major (FP64)
+  int* status;        // sticky status word (kStatusNotSPD)
+};
+
 // Work decomposition of one contraction launch (see mttkrp_kernels.hip).
 struct ContractPlan {
   int nM, nRed, nLoop, R;        // extents: output rows, reduction length, outer loop length
@@ -36,6 +52,7 @@ struct ContractPlan {
   int n_lb;                      // outer-loop blocks
   int slices;                    // partial slices = n_rg * n_lb
   bool vec;                      // 16-byte vector loads along a contiguous reduction
+  bool cm;                       // mode 2, m contiguous: row-interleaved 64-row tiles
   int64_t grid() const { return (int64_t)n_rg * n_mg * n_lb; }
 };
 
@@ -55,17 +72,34 @@ hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void
 hipError_t launch_quantize_slices(const float* x, int64_t I, int64_t J, int64_t K, uint8_t* q,
                                   uint8_t* qt, int32_t* exps, hipStream_t st);
 
-// FP64 Gram / solve pieces.
+// FP64 Gram / solve pieces.  `status` points to a zeroed 1 KiB device
+// block: word 0 is the sticky status, words 64..191 are the counters of the
+// kernels' last-workgroup reductions (each reduction returns its counter to
+// zero, so the block stays valid across launches and graph replays).
+// `ws` holds solve_ws_bytes(maxdim, R) bytes laid out for that maxdim; the
+// Gram matrices of the three factors persist there between launches.
+constexpr int kStatusWords = 256;
 size_t solve_ws_bytes(int64_t maxdim, int R);
+// Gram matrices of factors ma and (if mb >= 0) mb into their slots.
+hipError_t launch_grams(const float* const factors[3], const int64_t dims[3], int R, int ma, int mb, int64_t maxdim,
+                        void* ws, int* status, hipStream_t st);
+// Update of factor `mode` from its MTTKRP M, using the Gram slots of the two
+// other factors: Cholesky + inverse, F = M V^{-1}, lambda, normalised FP32
+// factor, and the Gram slot of the new factor.
+hipError_t launch_update(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
+                         int64_t maxdim, void* ws, int* status, hipStream_t st);
+// launch_update in two halves: the factorisation (Cholesky + inverse of V;
+// reads only the Gram slots of the other two factors, so it may run
+// concurrently with the mode's MTTKRP) and the rest (needs M).
+FactorArgs factor_args(const int64_t dims[3], int R, int mode, int64_t maxdim, void* ws, int* status);
+hipError_t launch_factor(const int64_t dims[3], int R, int mode, int64_t maxdim, void* ws, int* status,
+                         hipStream_t st);
+hipError_t launch_apply(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
+                        int64_t maxdim, void* ws, int* status, hipStream_t st);
+// launch_grams of the two other factors followed by launch_update.
 hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3], int R,
                              int mode, const float* M, float* factor_out, double* lambda,
                              void* ws, int* status, hipStream_t st);
-// The same update in two halves: Gram + Cholesky (needs only the other two
-// factors, so it can overlap the mode's MTTKRP), then solve + normalise.
-hipError_t launch_gram_chol(const float* const factors[3], const int64_t dims[3], int R, int mode,
-                            void* ws, int* status, hipStream_t st);
-hipError_t launch_solve_apply(const int64_t dims[3], int R, int mode, const float* M, float* factor_out,
-                              double* lambda, void* ws, int* status, hipStream_t st);
 size_t fit_ws_bytes(const int64_t dims[3]);
 hipError_t launch_fit(const void* X, int fmt, const int32_t* slice_exp, const int64_t dims[3],
                       const float* const factors[3], const double* lambda, int R,
@@ -78,11 +112,11 @@ struct mtk_ctx {
   int device = 0;
   void* ws = nullptr;             // workspace (partials, fragments, solve scratch)
   size_t ws_bytes = 0;
-  int* d_status = nullptr;        // sticky device status word
+  int* d_status = nullptr;        // sticky status word + reduction counters (kStatusWords ints)
   double* d_fit = nullptr;        // fit accumulators
   std::string last_error;
   void* graph_cache = nullptr;    // als_sweep graph cache (see api.hip)
-  hipStream_t side = nullptr;     // second stream of the captured sweep
+  hipStream_t side = nullptr;     // second stream of the captured sweep (factorisation)
   hipEvent_t fork_ev[3] = {nullptr, nullptr, nullptr};
   hipEvent_t join_ev[3] = {nullptr, nullptr, nullptr};
 };

@@ -75,9 +75,16 @@ template <int NV> struct XRegs<MTK_FP8_E4M3, NV> { uint32_t w[NV / 4]; };
 
 // Tiles kept in flight per wave: deeper for small tiles so that every CU has
 // enough bytes outstanding to cover the HBM latency.
+#ifndef MTK_PIPE_FP8
+#define MTK_PIPE_FP8 4
+#endif
+#ifndef MTK_PIPE_SMALL
+#define MTK_PIPE_SMALL 3
+#endif
 template <int PREC, int NV> struct PipeDepth {
   static constexpr int tile_vgprs = (PREC == MTK_FP8_E4M3) ? NV / 4 : NV;
-  static constexpr int value = tile_vgprs <= 8 ? 4 : (tile_vgprs <= 16 ? 3 : 2);
+  static constexpr int value = PREC == MTK_FP8_E4M3 ? MTK_PIPE_FP8
+                               : (tile_vgprs <= 8 ? 4 : (tile_vgprs <= 16 ? MTK_PIPE_SMALL : 2));
 };
 
 // Load this lane's nv reduction values of tile row `m` (global offset `off`
@@ -271,8 +278,10 @@ __device__ __forceinline__ void tile_mfma(f4 (&T)[NT], const XRegs<PREC, NV>& x,
   }
 }
 
+
 template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
 __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
+  extern __shared__ float dyn_lds[];
   constexpr int KW = 4 * NV;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -314,7 +323,6 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   // The block's weight rows F(l0..l1-1, :) in LDS (FP8 modes 1, 2: times the
   // slice scale 2^e_i of the loop index), read back with LDS loads so that
   // the only outstanding global loads in the loop are the X prefetches.
-  extern __shared__ float dyn_lds[];
   float* wl = dyn_lds;
   for (int e = threadIdx.x; e < (l1 - l0) * a.R; e += 256) {
     const int il = e / a.R;
@@ -412,6 +420,193 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
       const int orow = m0 + g * 4 + v;
       if (orow < a.nM) outp[(int64_t)orow * a.R + col] = acc[t][v];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mode 2 with a strided reduction (X(m, red, loop), m contiguous): row-
+// interleaved tiles.  A wave covers 64 consecutive rows m0 .. m0+63 as four
+// MFMA row tiles; tile c holds rows m0 + 4*rho + c (rho = 0..15).  Lane
+// (rho, g) reads, for each of its nv reduction values, one 16-byte vector
+// X(m0+4rho .. m0+4rho+3, red, loop): component c is its A-operand element
+// of tile c.  A load instruction thus reads four 256-byte contiguous runs,
+// and each fragment register feeds four MFMAs.
+// ---------------------------------------------------------------------------
+template <int NV> struct XRegsCM { f4 v[NV]; };
+
+template <int PREC, int NT> struct PipeDepthCM { static constexpr int value = NT == 1 ? 3 : 2; };
+
+template <int NV, bool full>
+__device__ __forceinline__ void load_x_cm(XRegsCM<NV>& x, const float* X, int64_t off, int64_t sRed,
+                                          bool row_ok, int red0, int nRed) {
+  const float* p = X + off;
+#pragma unroll
+  for (int e = 0; e < NV; ++e) {
+    // Rows come in aligned groups of four (nM % 4 == 0), so a vector is all
+    // in range or all out; out-of-range vectors read X[0..3] and are zeroed.
+    const bool ok = full || (row_ok && red0 + e < nRed);
+    const f4 u = *reinterpret_cast<const f4*>(ok ? p + (int64_t)e * sRed : X);
+    x.v[e] = ok ? u : zero4();
+  }
+}
+
+template <int PREC, int NT, int NV>
+__device__ __forceinline__ void tile_mfma_cm(f4 (&T)[4][NT], const XRegsCM<NV>& x,
+                                             const Frag<PREC, NT, NV>& fr) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[c][t] = zero4();
+  if constexpr (PREC == MTK_FP32) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          T[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.v[s][c], fr.f[t][s], T[c][t], 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int s = 0; s < NV / 8; ++s) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        bf16x8 ah, al;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 h, l;
+          split_bf16(x.v[s * 8 + e][c], h, l);
+          ah[e] = h;
+          al[e] = l;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) T[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, fr.hi[t][s], T[c][t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) T[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.lo[t][s], T[c][t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) T[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.hi[t][s], T[c][t], 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int PREC, int NT, int NV>
+__global__ __launch_bounds__(256) void contract_cm_kernel(KArgs a) {
+  extern __shared__ float dyn_lds[];
+  constexpr int KW = 4 * NV;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int rho = lane & 15;      // row of each interleaved tile / B-operand column
+  const int g = lane >> 4;        // reduction element group
+
+  int bid = blockIdx.x;
+  const int rg = bid % a.n_rg; bid /= a.n_rg;
+  const int mg = bid % a.n_mg; bid /= a.n_mg;
+  const int lb = bid;
+
+  const int cg = wave % a.ncg;
+  const int wred = (wave / a.ncg) % a.wr;
+  const int wm = wave / (a.ncg * a.wr);
+  const int cb = cg * NT * 16;
+  const int red_base = (rg * a.wr + wred) * KW;
+  const int red0 = red_base + g * NV;
+  const int m0 = (mg * a.mt_per_wg + wm) * 64;         // 64-row block of this wave
+  const int row4 = m0 + 4 * rho;                        // first of this lane's 4 rows
+  const bool row_ok = row4 < a.nM;
+  const bool tile_full = (m0 + 64 <= a.nM) && (red_base + KW <= a.nRed);
+
+  Frag<PREC, NT, NV> fr;
+  load_frag<PREC, NT, NV>(fr, a, red0, rho, cb);
+
+  f4 acc[4][NT];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[c][t] = zero4();
+
+  const int l0 = lb * a.loop_block;
+  const int l1 = min(a.nLoop, l0 + a.loop_block);
+  const float* X = static_cast<const float*>(a.X);
+  const int64_t off0 = (int64_t)(row_ok ? row4 : 0) + (int64_t)red0 * a.sRed;
+
+  float* wl = dyn_lds;
+  for (int e = threadIdx.x; e < (l1 - l0) * a.R; e += 256) wl[e] = a.weight[(int64_t)l0 * a.R + e];
+  __syncthreads();
+
+  auto step = [&](const XRegsCM<NV>& x, int it) {
+    f4 T[4][NT];
+    tile_mfma_cm<PREC, NT, NV>(T, x, fr);
+    const float* wr = wl + (it - l0) * a.R;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = cb + t * 16 + rho;
+      const float wv = wr[min(col, a.R - 1)];
+      const float w = col < a.R ? wv : 0.f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[c][t][v] = fmaf(w, T[c][t][v], acc[c][t][v]);
+    }
+  };
+
+  auto run = [&](auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    constexpr int D = PipeDepthCM<PREC, NT>::value;
+    if (l0 >= l1) return;
+    XRegsCM<NV> x[D];
+#pragma unroll
+    for (int d = 0; d < D - 1; ++d)
+      load_x_cm<NV, FULL>(x[d], X, off0 + (int64_t)min(l0 + d, l1 - 1) * a.sLoop, a.sRed, row_ok, red0, a.nRed);
+    for (int it = l0; it < l1; it += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int nx = min(it + d + D - 1, l1 - 1);
+        load_x_cm<NV, FULL>(x[(d + D - 1) % D], X, off0 + (int64_t)nx * a.sLoop, a.sRed, row_ok, red0, a.nRed);
+        __builtin_amdgcn_sched_barrier(0);
+        if (it + d < l1) step(x[d], it + d);
+      }
+    }
+  };
+  if (tile_full) run(std::true_type{});
+  else run(std::false_type{});
+
+  if (a.wr > 1) {
+    float* red_lds = dyn_lds + a.loop_block * a.R;   // [4 waves][4*NT*4][64]
+    auto at = [&](int w, int k) -> float& { return red_lds[(w * 16 * NT + k) * 64 + lane]; };
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) at(wave, (c * NT + t) * 4 + v) = acc[c][t][v];
+    __syncthreads();
+    if (wred != 0) return;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = (c * NT + t) * 4 + v;
+          float s = at(wave, k);
+          for (int q = 1; q < a.wr; ++q) s += at(wave + q * a.ncg, k);
+          acc[c][t][v] = s;
+        }
+  }
+
+  const int slice = rg * a.n_lb + lb;
+  float* outp = a.part + (int64_t)slice * a.nM * a.R;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = cb + t * 16 + rho;
+    if (col >= a.R) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // MFMA output row g*4+v of tile c is tensor row m0 + 4*(g*4+v) + c.
+        const int orow = m0 + 4 * (g * 4 + v) + c;
+        if (orow < a.nM) outp[(int64_t)orow * a.R + col] = acc[c][t][v];
+      }
   }
 }
 
@@ -531,8 +726,24 @@ hipError_t dispatch_nv(const KArgs& a, const ContractPlan& p, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
+template <int PREC, int NT>
+hipError_t launch_cm(const KArgs& a, const ContractPlan& p, hipStream_t st) {
+  constexpr int NV = 8;
+  if (p.nv != NV) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)a.loop_block * a.R + (a.wr > 1 ? 4 * 16 * NT * 64 : 0)) * sizeof(float);
+  hipLaunchKernelGGL((contract_cm_kernel<PREC, NT, NV>), dim3((unsigned)p.grid()), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
 template <int PREC>
 hipError_t dispatch_nt(const KArgs& a, const ContractPlan& p, hipStream_t st) {
+  if constexpr (PREC != MTK_FP8_E4M3) {
+    if (p.cm) {
+      if (p.ntw == 1) return launch_cm<PREC, 1>(a, p, st);
+      if (p.ntw == 2) return launch_cm<PREC, 2>(a, p, st);
+      return hipErrorInvalidValue;
+    }
+  }
   if constexpr (PREC == MTK_FP8_E4M3) {
     switch (p.ntw) {
       case 1: return dispatch_nv<PREC, 1>(a, p, st);
@@ -558,10 +769,36 @@ hipError_t dispatch_nt(const KArgs& a, const ContractPlan& p, hipStream_t st) {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Plan limits (compile-time so a build can be tuned without code changes):
+// widest per-lane reduction run for FP32 / bf16x3, and the workgroup count
+// the outer-loop split aims for.
+#ifndef MTK_NV_MAX
+#define MTK_NV_MAX 16
+#endif
+#ifndef MTK_WG_TARGET
+#define MTK_WG_TARGET 512
+#endif
+
 // Column length of the padded FP8 fragment codes: every window of the plan.
 inline int frag_red_pad(const ContractPlan& p) { return p.n_rg * p.wr * p.kw; }
 
 }  // namespace
+
+// Spread the outer loop over enough workgroups to fill the 256 CUs (two
+// resident per CU), long enough to amortise each workgroup's fragment load,
+// and keep the partial slices' traffic at a few percent of X (xbytes).
+static void set_loop_blocks(ContractPlan& p, double xbytes) {
+  const int64_t base = (int64_t)p.n_rg * p.n_mg;
+  const int64_t target = MTK_WG_TARGET;
+  int64_t n_lb = std::max<int64_t>(1, std::min<int64_t>(p.nLoop, cdiv(target, base)));
+  const double slice_bytes = (double)p.nM * p.R * 4.0 * 2.0;
+  const double cap = std::max(0.03 * xbytes, 4.0 * 1024 * 1024);
+  while (n_lb > 1 && (double)p.n_rg * n_lb * slice_bytes > cap) n_lb = cdiv(n_lb, 2);
+  p.loop_block = (int)cdiv(p.nLoop, n_lb);
+  p.loop_block = std::min(p.loop_block, std::max(1, 8192 / p.R));   // staged weights <= 32 KiB
+  p.n_lb = (int)cdiv(p.nLoop, p.loop_block);
+  p.slices = p.n_rg * p.n_lb;
+}
 
 ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16, bool transposed) {
   ContractPlan p{};
@@ -577,6 +814,24 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
   else if (transposed) { p.nM = (int)K; p.nRed = (int)J; p.nLoop = (int)I; p.sM = J; p.sRed = 1; p.sLoop = J * K; }
   else { p.nM = (int)K; p.nRed = (int)J; p.nLoop = (int)I; p.sM = 1; p.sRed = K; p.sLoop = J * K; }
 
+  // Mode 2 of an FP32 tensor with k contiguous: row-interleaved tiles of 64
+  // rows read with 16-byte vectors (needs 16-byte aligned rows: K % 4 == 0).
+  if (mode == 2 && !transposed && prec != MTK_FP8_E4M3 && x_aligned16 && K % 4 == 0) {
+    p.cm = true;
+    p.ncg = p.nt <= 2 ? 1 : (p.nt <= 4 ? 2 : 4);
+    p.ntw = (int)cdiv(p.nt, p.ncg);
+    p.nv = 8;
+    p.kw = 32;
+    const int64_t windows = cdiv(p.nRed, p.kw);
+    p.wr = std::min<int>(4 / p.ncg, windows >= 4 ? 4 : (windows >= 2 ? 2 : 1));
+    p.mt_per_wg = 4 / (p.ncg * p.wr);
+    p.n_rg = (int)cdiv(p.nRed, (int64_t)p.wr * p.kw);
+    p.n_mg = (int)cdiv(cdiv(p.nM, 64), p.mt_per_wg);
+    set_loop_blocks(p, I * J * K * 4.0);
+    p.vec = true;
+    return p;
+  }
+
   // Fragment registers per lane: nt*nv (FP32, BF16X3 hi+lo) or nt*nv/4 (FP8); keep <= 64.
   int nv;
   if (prec == MTK_FP8_E4M3) {
@@ -584,7 +839,7 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
     while (nv > 32 && p.ntw * nv / 2 > 64) nv /= 2;      // hi + lo terms
     while (nv > 32 && 4 * (nv / 2) >= p.nRed) nv /= 2;
   } else {
-    nv = 64;
+    nv = MTK_NV_MAX;
     while (nv > 8 && p.ntw * nv > 64) nv /= 2;
     while (nv > 8 && 4 * (nv / 2) >= p.nRed) nv /= 2;
   }
@@ -602,20 +857,7 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
   p.n_rg = (int)cdiv(p.nRed, (int64_t)p.wr * p.kw);
   p.n_mg = (int)cdiv(cdiv(p.nM, 16), p.mt_per_wg);
 
-  // Spread the outer loop over enough workgroups to fill the 256 CUs (two
-  // resident per CU), long enough to amortise each workgroup's fragment load,
-  // and keep the partial slices' traffic at a few percent of X.
-  const int64_t base = (int64_t)p.n_rg * p.n_mg;
-  const int64_t target = 512;            // two resident workgroups per CU
-  int64_t n_lb = std::max<int64_t>(1, std::min<int64_t>(p.nLoop, cdiv(target, base)));
-  const double xbytes = (double)I * J * K * (prec == MTK_FP8_E4M3 ? 1.0 : 4.0);
-  const double slice_bytes = (double)p.nM * R * 4.0 * 2.0;
-  const double cap = std::max(0.03 * xbytes, 4.0 * 1024 * 1024);
-  while (n_lb > 1 && (double)p.n_rg * n_lb * slice_bytes > cap) n_lb = cdiv(n_lb, 2);
-  p.loop_block = (int)cdiv(p.nLoop, n_lb);
-  p.loop_block = std::min(p.loop_block, std::max(1, 8192 / R));   // staged weights <= 32 KiB
-  p.n_lb = (int)cdiv(p.nLoop, p.loop_block);
-  p.slices = p.n_rg * p.n_lb;
+  set_loop_blocks(p, (double)I * J * K * (prec == MTK_FP8_E4M3 ? 1.0 : 4.0));
   const int elem = prec == MTK_FP8_E4M3 ? 1 : 4;
   p.vec = (p.sRed == 1) && x_aligned16 && ((int64_t)p.nRed * elem % 16 == 0);
   return p;

@@ -140,16 +140,22 @@ size_t host_bytes(const Req& r) {
   return b;
 }
 
-size_t scratch_bytes(const int64_t dims[3], int R, int prec) {
+// Contraction / fit scratch of a request, rounded to 256 bytes.
+size_t contract_region_bytes(const int64_t dims[3], int R, int prec) {
   size_t b = 0;
   for (int m = 0; m < 3; ++m) {
     mtk::ContractPlan p = mtk::make_plan(dims, R, m, prec, true);
     b = std::max(b, mtk::contract_ws_bytes(p, prec));
   }
-  const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
-  b = std::max(b, mtk::solve_ws_bytes(maxdim, R));
   b = std::max(b, mtk::fit_ws_bytes(dims));
-  return b;
+  return r256(b);
+}
+
+// The solve region (which keeps the Gram matrices across the MTTKRPs)
+// follows the contraction region.
+size_t scratch_bytes(const int64_t dims[3], int R, int prec) {
+  const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
+  return contract_region_bytes(dims, R, prec) + mtk::solve_ws_bytes(maxdim, R);
 }
 
 size_t device_bytes(const int64_t dims[3], int R, int prec) {
@@ -214,13 +220,16 @@ struct mtk_server {
           hipSuccess)
         return e;
     const float* cf[3] = {f[0], f[1], f[2]};
+    void* solve_ws = static_cast<char*>(scratch) + contract_region_bytes(r.dims, R, r.prec);
+    if (r.sweeps > 0 && (e = mtk::launch_grams(cf, r.dims, R, 1, 2, maxdim, solve_ws, s.d_status, s.st)) != hipSuccess)
+      return e;
     for (int sw = 0; sw < r.sweeps; ++sw) {
       for (int n = 0; n < 3; ++n) {
         const float* fr = n == 2 ? f[1] : f[2];
         const float* wt = n == 0 ? f[1] : f[0];
         mtk::ContractPlan p = mtk::make_plan(r.dims, R, n, r.prec, true);
         if ((e = mtk::launch_contract(p, r.prec, n, X, nullptr, fr, wt, M, scratch, s.st)) != hipSuccess) return e;
-        if ((e = mtk::launch_gram_solve(cf, r.dims, R, n, M, f[n], lam, scratch, s.d_status, s.st)) != hipSuccess)
+        if ((e = mtk::launch_update(r.dims, R, n, M, f[n], lam, maxdim, solve_ws, s.d_status, s.st)) != hipSuccess)
           return e;
       }
     }
@@ -345,7 +354,9 @@ mtk_status mtk_server_create(mtk_server** out, int device, uint64_t budget_bytes
   for (auto& sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc(&sl.d_status, 256) != hipSuccess || hipMalloc(&sl.d_fit, 256) != hipSuccess) {
+        hipMalloc(&sl.d_status, mtk::kStatusWords * sizeof(int)) != hipSuccess ||
+        hipMemset(sl.d_status, 0, mtk::kStatusWords * sizeof(int)) != hipSuccess ||
+        hipMalloc(&sl.d_fit, 256) != hipSuccess) {
       mtk_server_destroy(s);
       return MTK_EHIP;
     }

@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmttkrp.so")
+LIB_PATH = os.environ.get("MTK_LIBRARY") or os.path.join(_HERE, "libmttkrp.so")
 
 MTK_OK, MTK_EINVAL, MTK_ENOMEM, MTK_EHIP, MTK_ENOTSPD, MTK_EUNSUPPORTED, MTK_EBUDGET, MTK_EAGAIN = \
     0, -1, -2, -3, -4, -5, -6, -7

@@ -25,7 +25,7 @@ def _small(dims=(40, 36, 32), rank=4, R=4, noise=1e-4, seed=21):
     return w, synth.tensor(w, threads=4), synth.init_factors(w)
 
 
-@pytest.mark.parametrize("R", [1, 8, 37, 128])
+@pytest.mark.parametrize("R", [1, 8, 20, 32, 37, 64, 128])
 def test_gram_solve_matches_oracle(ctx, R):
     from gpu_util import dev, host, rel
     w, X, facs = _small(dims=(150, 140, 130), rank=min(R, 8), R=R, seed=R)
@@ -42,13 +42,30 @@ def test_gram_solve_matches_oracle(ctx, R):
         assert rel(raw @ V, M) <= 1e-6
 
 
-def test_gram_solve_not_spd(ctx):
+def test_gram_solve_many_row_blocks(ctx):
+    # A 1100-row factor is summed in 16 row-block partials: the gather of V
+    # takes its general path (more than 8 partials per factor).
+    from gpu_util import dev, host, rel
+    w, X, facs = _small(dims=(1100, 70, 90), rank=8, R=8, seed=11)
+    g = np.random.default_rng(11)
+    for mode in (1, 2):
+        M = g.standard_normal((w.dims[mode], 8)).astype(np.float32)
+        f_out, lam = ctx.gram_solve([dev(f) for f in facs], w.dims, mode, dev(M))
+        ctx.check()
+        An, lo = oracle.gram_solve(facs, M, mode)
+        assert rel(host(lam), lo) <= 1e-10
+        assert rel(host(f_out), An) <= 1e-6
+
+
+@pytest.mark.parametrize("R", [4, 24, 40])
+def test_gram_solve_not_spd(ctx, R):
+    # One factorisation path each: register-resident R <= 16, R <= 32, blocked.
     from gpu_util import dev
     from paper_2411_04785_amd.mttkrp import NotSPDError
-    w, X, facs = _small()
+    w, X, facs = _small(dims=(60, 50, 40), rank=4, R=R, seed=R)
     facs = [f.copy() for f in facs]
     facs[1][:, 2] = 0.0          # zero column -> zero row/column of V -> pivot 0
-    M = np.ones((w.dims[0], 4), np.float32)
+    M = np.ones((w.dims[0], R), np.float32)
     ctx.gram_solve([dev(f) for f in facs], w.dims, 0, dev(M))
     with pytest.raises(NotSPDError):
         ctx.check()

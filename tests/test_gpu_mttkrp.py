@@ -69,6 +69,8 @@ RAGGED = [
     ((17, 300, 18), 96),
     ((64, 96, 128), 16),
     ((5, 7, 1000), 33),
+    ((70, 300, 132), 48),
+    ((300, 130, 68), 24),
 ]
 
 
