@@ -4,8 +4,8 @@
 Default workload (N=1): 512 x 512 x 512 FP32 tensor, rank-32 CP model plus
 N(0, 1e-4) noise, R = 32 factors iid N(0,1) (synthetic, seeded).  One step =
 one CP-ALS sweep on the device: for each mode an MTTKRP (HIP contraction +
-fixed-order split-K reduce) followed by the FP64 Gram / Cholesky / solve /
-normalise update.  ``value`` is algorithmic MTTKRP GFLOP/s of the whole
+fixed-order split-K reduce) followed by the FP64 Gram / LDL^T (Cholesky)
+inverse / solve / normalise update.  ``value`` is algorithmic MTTKRP GFLOP/s of the whole
 sweep (3 * 2*I*J*K*R flop per step over the step time, solves included).
 
 Also measured live (HIP events on the library's stream): each mode's MTTKRP
@@ -234,6 +234,11 @@ def main():
     log(f"[bench] generated in {time.perf_counter() - t0:.1f} s; uploading")
 
     dev = torch.device("cuda:0")
+    # All library calls and the timing events go to one dedicated stream (a
+    # caller's own stream, as a user of the library would pass it), not the
+    # legacy default stream.
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
     ctx = Context(0)
     Xd = torch.from_numpy(X).to(dev)
     slice_exp = None
@@ -245,13 +250,14 @@ def main():
     else:
         Xrun = Xd
     f0 = [torch.from_numpy(f).to(dev) for f in facs]
-    stream = torch.cuda.current_stream()
 
     # ---- per-mode MTTKRP timing (HIP events on the library's stream) ----
     mode_ms = []
     outs = []
     for mode in range(3):
         out = ctx.mttkrp(Xrun, f0, mode, prec, slice_exp=slice_exp, X_t=Xt)
+        for _ in range(10):         # untimed: steady state (page tables, clocks)
+            ctx.mttkrp(Xrun, f0, mode, prec, out=out, slice_exp=slice_exp, X_t=Xt)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)

@@ -26,7 +26,7 @@
  *    enqueued asynchronously on it; arguments are validated synchronously.
  *  - Invalid arguments return MTK_EINVAL with a message in mtk_last_error
  *    and enqueue nothing.  Errors detected on the device (a non-positive
- *    Cholesky pivot) set a sticky status word that mtk_check returns.
+ *    elimination pivot) set a sticky status word that mtk_check returns.
  *  - NaN / Inf inputs propagate to the outputs; they are not checked.
  *  - A context is not thread-safe: use one per host thread.  All entry
  *    points of one context must use the same device.
@@ -98,7 +98,8 @@ mtk_status mtk_destroy(mtk_ctx* ctx);
 const char* mtk_last_error(const mtk_ctx* ctx);
 
 /* Synchronise `stream`, then return and clear the sticky device status:
- * MTK_OK, or MTK_ENOTSPD if a Cholesky pivot was <= 0 since the last check. */
+ * MTK_OK, or MTK_ENOTSPD if an elimination pivot of V was <= 0 since the
+ * last check (V is then not positive definite). */
 mtk_status mtk_check(mtk_ctx* ctx, void* stream);
 
 /* Reserve workspace for MTTKRPs / solves / sweeps up to these sizes, so
@@ -133,7 +134,9 @@ mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[
 
 /* Normal-equation update of one factor (FP64 on the device).
  *  V = *_{m != mode} A_m^T A_m  (R x R, FP64, from the FP32 factors)
- *  V = L L^T (Cholesky), W = L^{-1}, V^{-1} = W^T W, F = M V^{-1} (FP64)
+ *  V^{-1} by symmetric elimination: the LDL^T (square-root-free Cholesky)
+ *  factorisation of V carried out in Gauss-Jordan form, which also clears
+ *  above the diagonal and so leaves V^{-1}; F = M V^{-1} (all FP64)
  *  lambda_out[r] = ||F(:,r)||_2 (FP64); factor_out = F(:,r)/lambda_r cast
  *  to FP32 (a column with lambda_r == 0 is written unscaled).
  *  factors    : three device pointers (factors[mode] not read, may be NULL).

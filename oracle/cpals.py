@@ -13,7 +13,7 @@ on this method; these are the standard definitions.
 
 The oracle solves the normal equations with a general LU solve
 (``numpy.linalg.solve``), deliberately a different factorisation from the
-Cholesky the GPU uses.
+symmetric (LDL^T) elimination the GPU uses.
 """
 
 from __future__ import annotations

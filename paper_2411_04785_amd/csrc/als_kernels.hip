@@ -3,8 +3,9 @@
 // Given the FP32 factors and the FP32 MTTKRP M (n x R) of mode `mode`:
 //   G_m = A_m^T A_m, the Gram matrix of factor m (FP64 sums of FP32 products)
 //   V = G_a * G_b (Hadamard) over the two other modes
-//   V = L L^T (Cholesky, FP64; a pivot <= 0 sets the sticky NOT-SPD status)
-//   W = L^{-1}, V^{-1} = W^T W (FP64)
+//   V^{-1} by symmetric elimination: the LDL^T (square-root-free Cholesky)
+//   factorisation in Gauss-Jordan form (FP64; a pivot <= 0 sets the sticky
+//   NOT-SPD status)
 //   F = M V^{-1} (FP64)
 //   lambda_r = ||F(:,r)||_2, factor = F(:,r) / lambda_r cast to FP32.
 // The Gram matrix of the factor just written is formed (as per-row-block
@@ -30,7 +31,8 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 // 16 x 16 tiles of the lower triangle of an R x R Gram matrix.
 __host__ __device__ inline int gram_pairs(int R) { const int t = (R + 15) / 16; return t * (t + 1) / 2; }
 // Row blocks of a Gram matrix (one partial each): about 128 workgroups in
-// all (tile pairs x blocks), at most kGramBlocksMax blocks.
+// all (tile pairs x blocks), at most kGramBlocksMax blocks.  Their partials
+// are summed where V is gathered (one workgroup), so fewer is cheaper there.
 __host__ __device__ inline int gram_blocks(int64_t n, int R) {
   int64_t b = 128 / gram_pairs(R);
   b = b < 1 ? 1 : (b > kGramBlocksMax ? kGramBlocksMax : b);
@@ -99,15 +101,11 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ F0,
 }
 
 
-// Stand-alone factorisation: one workgroup.
-__global__ __launch_bounds__(256) void chol_inv_kernel(FactorArgs f) {
+// Stand-alone factorisation (V^{-1}): one workgroup.
+template <int B>
+__global__ __launch_bounds__(256) void gj_inv_kernel(FactorArgs f) {
   extern __shared__ double lds[];
-  factor_v_inv(f, lds);
-}
-
-template <int RP>
-__global__ __launch_bounds__(256) void chol_inv_small_kernel(FactorArgs f) {
-  factor_v_inv_small<RP>(f);
+  factor_gj<B>(f, lds);
 }
 
 // F = M V^{-1}: workgroup (row block of 64, column block of 16); thread
@@ -280,12 +278,17 @@ FactorArgs factor_args(const int64_t dims[3], int R, int mode, int64_t maxdim, v
 hipError_t launch_factor(const int64_t dims[3], int R, int mode, int64_t maxdim, void* ws, int* status,
                          hipStream_t st) {
   const FactorArgs f = factor_args(dims, R, mode, maxdim, ws, status);
-  if (R <= 16)
-    hipLaunchKernelGGL(chol_inv_small_kernel<16>, dim3(1), dim3(256), 0, st, f);
-  else if (R <= 32)
-    hipLaunchKernelGGL(chol_inv_small_kernel<32>, dim3(1), dim3(256), 0, st, f);
-  else
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), factor_lds_bytes(R), st, f);
+  const size_t lds = factor_gj_lds_bytes(R);
+  switch ((R + 15) / 16) {
+    case 1: hipLaunchKernelGGL(gj_inv_kernel<1>, dim3(1), dim3(256), lds, st, f); break;
+    case 2: hipLaunchKernelGGL(gj_inv_kernel<2>, dim3(1), dim3(256), lds, st, f); break;
+    case 3: hipLaunchKernelGGL(gj_inv_kernel<3>, dim3(1), dim3(256), lds, st, f); break;
+    case 4: hipLaunchKernelGGL(gj_inv_kernel<4>, dim3(1), dim3(256), lds, st, f); break;
+    case 5: hipLaunchKernelGGL(gj_inv_kernel<5>, dim3(1), dim3(256), lds, st, f); break;
+    case 6: hipLaunchKernelGGL(gj_inv_kernel<6>, dim3(1), dim3(256), lds, st, f); break;
+    case 7: hipLaunchKernelGGL(gj_inv_kernel<7>, dim3(1), dim3(256), lds, st, f); break;
+    default: hipLaunchKernelGGL(gj_inv_kernel<8>, dim3(1), dim3(256), lds, st, f); break;
+  }
   return hipGetLastError();
 }
 

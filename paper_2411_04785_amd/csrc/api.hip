@@ -309,7 +309,7 @@ mtk_status mtk_fit(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3
 
 // One CP-ALS sweep (modes 0, 1, 2) enqueued on `st`, optionally followed by
 // the fit partial sums into c->d_fit.  M buffer and scratch come from ws.
-// Per mode: MTTKRP, then the update (Cholesky + inverse of V from the Gram
+// Per mode: MTTKRP, then the update (LDL^T / Gauss-Jordan inverse of V from the Gram
 // matrices kept in the solve region, F = M V^{-1}, normalise, and the Gram
 // matrix of the new factor); for large R the factorisation runs on the
 // side stream concurrently with the MTTKRP.  The Gram matrices of factors 1 and 2 must be

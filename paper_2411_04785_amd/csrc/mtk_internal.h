@@ -23,7 +23,7 @@ constexpr int kStatusNotSPD = 1;
 // with room for this many row blocks.
 constexpr int kGramBlocksMax = 16;
 
-// Inputs / outputs of the FP64 factorisation of one update's V (see
+// Inputs / outputs of the FP64 inversion of one update's V (see
 // factor_device.h): V^{-1} from the Gram partials of the two other factors.
 struct FactorArgs {
   const double* pa;   // Gram partials of the first other factor
@@ -84,13 +84,15 @@ size_t solve_ws_bytes(int64_t maxdim, int R);
 hipError_t launch_grams(const float* const factors[3], const int64_t dims[3], int R, int ma, int mb, int64_t maxdim,
                         void* ws, int* status, hipStream_t st);
 // Update of factor `mode` from its MTTKRP M, using the Gram slots of the two
-// other factors: Cholesky + inverse, F = M V^{-1}, lambda, normalised FP32
-// factor, and the Gram slot of the new factor.
+// other factors: V^{-1} (LDL^T elimination in Gauss-Jordan form),
+// F = M V^{-1}, lambda, the normalised FP32 factor, and the Gram slot of the
+// new factor.
 hipError_t launch_update(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
                          int64_t maxdim, void* ws, int* status, hipStream_t st);
-// launch_update in two halves: the factorisation (Cholesky + inverse of V;
-// reads only the Gram slots of the other two factors, so it may run
-// concurrently with the mode's MTTKRP) and the rest (needs M).
+// launch_update in two halves: the factorisation (V^{-1} by LDL^T /
+// Gauss-Jordan elimination; reads only the Gram slots of the other two
+// factors, so it may run concurrently with the mode's MTTKRP) and the rest
+// (needs M).
 FactorArgs factor_args(const int64_t dims[3], int R, int mode, int64_t maxdim, void* ws, int* status);
 hipError_t launch_factor(const int64_t dims[3], int R, int mode, int64_t maxdim, void* ws, int* status,
                          hipStream_t st);
