@@ -357,10 +357,14 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
     constexpr int D = PipeDepth<PREC, NV>::value;
     if (l0 >= l1) return;
     XRegs<PREC, NV> x[D];
+    // The prologue loads stay in tile order: the loop head's wait is shared
+    // by this path and the back edge, and must only need the oldest tile.
 #pragma unroll
-    for (int d = 0; d < D - 1; ++d)
+    for (int d = 0; d < D - 1; ++d) {
       load_x<PREC, NV, CONTIG, VEC, FULL>(x[d], a.X, off0 + (int64_t)min(l0 + d, l1 - 1) * a.sLoop, a.sRed,
                                           row_ok, red0, a.nRed);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     for (int it = l0; it < l1; it += D) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
@@ -554,8 +558,10 @@ __global__ __launch_bounds__(256) void contract_cm_kernel(KArgs a) {
     if (l0 >= l1) return;
     XRegsCM<NV> x[D];
 #pragma unroll
-    for (int d = 0; d < D - 1; ++d)
+    for (int d = 0; d < D - 1; ++d) {
       load_x_cm<NV, FULL>(x[d], X, off0 + (int64_t)min(l0 + d, l1 - 1) * a.sLoop, a.sRed, row_ok, red0, a.nRed);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     for (int it = l0; it < l1; it += D) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
@@ -778,6 +784,10 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 #ifndef MTK_WG_TARGET
 #define MTK_WG_TARGET 512
 #endif
+// Largest staged weight block (floats) of a workgroup.
+#ifndef MTK_STAGE_FLOATS
+#define MTK_STAGE_FLOATS 8192
+#endif
 
 // Column length of the padded FP8 fragment codes: every window of the plan.
 inline int frag_red_pad(const ContractPlan& p) { return p.n_rg * p.wr * p.kw; }
@@ -795,7 +805,7 @@ static void set_loop_blocks(ContractPlan& p, double xbytes) {
   const double cap = std::max(0.03 * xbytes, 4.0 * 1024 * 1024);
   while (n_lb > 1 && (double)p.n_rg * n_lb * slice_bytes > cap) n_lb = cdiv(n_lb, 2);
   p.loop_block = (int)cdiv(p.nLoop, n_lb);
-  p.loop_block = std::min(p.loop_block, std::max(1, 8192 / p.R));   // staged weights <= 32 KiB
+  p.loop_block = std::min(p.loop_block, std::max(1, MTK_STAGE_FLOATS / p.R));   // staged weights
   p.n_lb = (int)cdiv(p.nLoop, p.loop_block);
   p.slices = p.n_rg * p.n_lb;
 }
