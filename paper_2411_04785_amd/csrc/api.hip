@@ -236,7 +236,8 @@ mtk_status mtk_quantize_fp8(mtk_ctx* c, const float* x, const int64_t dims[3], u
 }
 
 static mtk_status mttkrp_impl(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], int R, int mode,
-                              int prec, float* out, void* ws, hipStream_t st) {
+                              int prec, float* out, void* ws, hipStream_t st,
+                              const mtk::FactorArgs* job = nullptr) {
   const float* fr;     // fragment factor (inside the MFMA)
   const float* wt;     // weight factor (epilogue)
   if (mode == 0) { fr = factors[2]; wt = factors[1]; }
@@ -245,7 +246,7 @@ static mtk_status mttkrp_impl(mtk_ctx* c, const mtk_tensor* X, const float* cons
   const bool tr = mode == 2 && X->fmt == MTK_FP8_E4M3 && X->data_t != nullptr;
   const void* data = tr ? X->data_t : X->data;
   ContractPlan p = mtk::make_plan(X->dims, R, mode, prec, aligned16(data), tr);
-  hipError_t e = mtk::launch_contract(p, prec, mode, data, X->slice_exp, fr, wt, out, ws, st);
+  hipError_t e = mtk::launch_contract(p, prec, mode, data, X->slice_exp, fr, wt, out, ws, st, job);
   if (e != hipSuccess) return hip_fail(c, e, "mttkrp launch");
   return MTK_OK;
 }
@@ -329,9 +330,11 @@ static mtk_status enqueue_initial_grams(mtk_ctx* c, const mtk_tensor* X, float* 
   return MTK_OK;
 }
 
-// Smallest R whose factorisation runs on the side stream.  Measured: at
-// R = 32 the one-workgroup factorisation, slowed several-fold by sharing a
-// CU with the contraction, ends after it; from R = 64 on it is hidden.
+// How an update's factorisation (V^{-1}) is placed against the MTTKRP it
+// does not depend on.  R <= kJobMaxRank: as one extra workgroup of the
+// contraction launch.  R >= kOverlapMinRank: on the side stream (a
+// cross-stream dependency costs about 10 us, hidden from R = 64 on).  In
+// between: its own launch after the MTTKRP.
 constexpr int kOverlapMinRank = 41;
 
 static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int R,
@@ -343,6 +346,14 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
   const float* cf[3] = {factors[0], factors[1], factors[2]};
   const bool overlap = R >= kOverlapMinRank;
   for (int n = 0; n < 3; ++n) {
+    if (R <= mtk::kJobMaxRank) {
+      const mtk::FactorArgs f = mtk::factor_args(X->dims, R, n, maxdim, solve_ws, c->d_status);
+      mtk_status s = mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st, &f);
+      if (s != MTK_OK) return s;
+      hipError_t e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st);
+      if (e != hipSuccess) return hip_fail(c, e, "update launch");
+      continue;
+    }
     if (!overlap) {
       mtk_status s = mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st);
       if (s != MTK_OK) return s;

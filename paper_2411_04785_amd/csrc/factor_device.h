@@ -25,10 +25,10 @@ __device__ inline void tile_pair(int t, int& tr, int& ts) {
 // 16 x 16 tile of G is the block-ordered sum of its partials.  Each round a
 // thread loads every partial of U entries (NQ >= partial count, loads past
 // it predicated off) before summing, so a round costs one memory latency.
-template <int NQ>
+// NQ <= kGramBlocksMax.
+template <int NQ, int U>
 __device__ inline void gather_v_nq(const FactorArgs& f, int Rp, double* A, int ld) {
   using fdev::tile_pair;
-  constexpr int U = 32 / NQ;
   const int R = f.R, na = f.na, nb = f.nb;
   const double* __restrict__ Pa = f.pa;
   const double* __restrict__ Pb = f.pb;
@@ -61,12 +61,19 @@ __device__ inline void gather_v_nq(const FactorArgs& f, int Rp, double* A, int l
   }
 }
 
-// All threads of the workgroup take part; the caller synchronises.
+// All threads of the workgroup take part; the caller synchronises.  LEAN:
+// one entry per round (fewer registers, for a workgroup that rides along in
+// another kernel).
+template <bool LEAN>
 __device__ inline void gather_v(const FactorArgs& f, int Rp, double* A, int ld) {
   const int nq = f.na > f.nb ? f.na : f.nb;
-  if (nq <= 4) gather_v_nq<4>(f, Rp, A, ld);
-  else if (nq <= 8) gather_v_nq<8>(f, Rp, A, ld);
-  else gather_v_nq<kGramBlocksMax>(f, Rp, A, ld);
+  if constexpr (LEAN) {
+    gather_v_nq<kGramBlocksMax, 1>(f, Rp, A, ld);
+  } else {
+    if (nq <= 4) gather_v_nq<4, 8>(f, Rp, A, ld);
+    else if (nq <= 8) gather_v_nq<8, 4>(f, Rp, A, ld);
+    else gather_v_nq<kGramBlocksMax, 2>(f, Rp, A, ld);
+  }
 }
 
 // Inversion of V in place (any R <= 128; Rp = 16*B) by symmetric
@@ -83,17 +90,17 @@ __device__ inline void gather_v(const FactorArgs& f, int Rp, double* A, int ld) 
 // after which A holds V^{-1}.  The owners of row k and column k publish
 // them (start-of-step values) in a double-buffered LDS slot, so each step
 // needs one barrier.  Padding rows/columns (identity) pass through.
-template <int B>
+template <int B, bool LEAN = false>
 __device__ inline void factor_gj(const FactorArgs& f, double* lds) {
   constexpr int RP = 16 * B;
   constexpr int LD = RP + 1;
-  __shared__ double bc[2][2][RP];                   // [buffer][column k | row k]
   const int R = f.R;
   const int tid = threadIdx.x;
   const int ti = tid >> 4, tj = tid & 15;
   const int i0 = ti * B, j0 = tj * B;
   double* A = lds;                                  // RP x LD, lower triangle of V
-  gather_v(f, RP, A, LD);
+  double* bc = lds + RP * LD;                       // [buffer][column k | row k][RP]
+  gather_v<LEAN>(f, RP, A, LD);
   __syncthreads();
   double a[B][B];
 #pragma unroll
@@ -111,21 +118,21 @@ __device__ inline void factor_gj(const FactorArgs& f, double* lds) {
       const int buf = k & 1;
       if (tj == kb) {
 #pragma unroll
-        for (int u = 0; u < B; ++u) bc[buf][0][i0 + u] = a[u][kk];
+        for (int u = 0; u < B; ++u) bc[(2 * buf) * RP + i0 + u] = a[u][kk];
       }
       if (ti == kb) {
 #pragma unroll
-        for (int v = 0; v < B; ++v) bc[buf][1][j0 + v] = a[kk][v];
+        for (int v = 0; v < B; ++v) bc[(2 * buf + 1) * RP + j0 + v] = a[kk][v];
       }
       __syncthreads();
-      const double p = bc[buf][0][k];
+      const double p = bc[(2 * buf) * RP + k];
       bad |= !(p > 0.0);                           // uniform: every thread reads the same p
       const double r = 1.0 / p;
       double ci[B], rj[B];
 #pragma unroll
-      for (int u = 0; u < B; ++u) ci[u] = bc[buf][0][i0 + u] * r;
+      for (int u = 0; u < B; ++u) ci[u] = bc[(2 * buf) * RP + i0 + u] * r;
 #pragma unroll
-      for (int v = 0; v < B; ++v) rj[v] = bc[buf][1][j0 + v];
+      for (int v = 0; v < B; ++v) rj[v] = bc[(2 * buf + 1) * RP + j0 + v];
 #pragma unroll
       for (int u = 0; u < B; ++u)
 #pragma unroll
@@ -155,10 +162,11 @@ __device__ inline void factor_gj(const FactorArgs& f, double* lds) {
     }
 }
 
-// LDS of factor_gj (bytes): the gathered lower triangle.
+// LDS of factor_gj (bytes): the gathered lower triangle and the two
+// broadcast slots.
 __host__ __device__ inline size_t factor_gj_lds_bytes(int R) {
   const size_t Rp = (size_t)((R + 15) & ~15);
-  return Rp * (Rp + 1) * sizeof(double);
+  return (Rp * (Rp + 1) + 4 * Rp) * sizeof(double);
 }
 
 }  // namespace mtk

@@ -64,9 +64,14 @@ size_t contract_ws_bytes(const ContractPlan& p, int prec);
 // (element (i,j,k) at (i*K + k)*J + j), which makes the reduction over j contiguous.
 ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16,
                        bool transposed = false);
+// `job` (optional, R <= kJobMaxRank): the inversion of an update's V, run
+// by one extra workgroup of the same launch so that it overlaps the
+// contraction (results in job->vinv once the launch has completed).
+constexpr int kJobMaxRank = 32;
 hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void* X,
                            const int32_t* slice_exp, const float* frag_src,
-                           const float* weight, float* out, void* ws, hipStream_t st);
+                           const float* weight, float* out, void* ws, hipStream_t st,
+                           const FactorArgs* job = nullptr);
 
 // FP8 tensor preparation (per mode-1 slice power-of-two scaled e4m3).
 hipError_t launch_quantize_slices(const float* x, int64_t I, int64_t J, int64_t K, uint8_t* q,

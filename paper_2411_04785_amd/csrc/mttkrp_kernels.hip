@@ -29,6 +29,7 @@
 // (dims, R, mode, precision) alone, so results are bitwise reproducible.
 
 #include "mtk_internal.h"
+#include "factor_device.h"
 #include "fp8_codec.h"
 
 #include <algorithm>
@@ -55,7 +56,22 @@ struct KArgs {
   int wr, mt_per_wg, n_rg, n_mg, loop_block, n_lb;
   int ncg;                    // column groups: waves splitting R over the same tile
   int mode;
+  int job_on;                 // 1: workgroup 0 inverts job's V, the rest shift by one
+  FactorArgs job;
 };
+
+// The inversion of an update's V (R <= kJobMaxRank) run by one extra
+// workgroup of a contraction launch, so that it overlaps the contraction
+// with no launch or stream dependency of its own.  It is workgroup 0, the
+// first dispatched, so it starts with the contraction rather than in its
+// last wave.  Only the instantiations with at most 2 column tiles (R <= 32)
+// carry it.
+__device__ __forceinline__ bool run_job(const KArgs& a, float* lds) {
+  if (!a.job_on || blockIdx.x != 0) return false;
+  if (a.job.R <= 16) factor_gj<1, true>(a.job, reinterpret_cast<double*>(lds));
+  else factor_gj<2, true>(a.job, reinterpret_cast<double*>(lds));
+  return true;
+}
 
 __device__ __forceinline__ f4 zero4() { return f4{0.f, 0.f, 0.f, 0.f}; }
 
@@ -282,6 +298,9 @@ __device__ __forceinline__ void tile_mfma(f4 (&T)[NT], const XRegs<PREC, NV>& x,
 template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
 __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   extern __shared__ float dyn_lds[];
+  if constexpr (NT <= 2) {
+    if (run_job(a, dyn_lds)) return;
+  }
   constexpr int KW = 4 * NV;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -290,7 +309,7 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
 
   // Workgroup -> (reduction group, M group, loop block); the reduction group
   // varies fastest so neighbouring workgroups read neighbouring windows.
-  int bid = blockIdx.x;
+  int bid = (int)blockIdx.x - a.job_on;
   const int rg = bid % a.n_rg; bid /= a.n_rg;
   const int mg = bid % a.n_mg; bid /= a.n_mg;
   const int lb = bid;
@@ -496,13 +515,16 @@ __device__ __forceinline__ void tile_mfma_cm(f4 (&T)[4][NT], const XRegsCM<NV>& 
 template <int PREC, int NT, int NV>
 __global__ __launch_bounds__(256) void contract_cm_kernel(KArgs a) {
   extern __shared__ float dyn_lds[];
+  if constexpr (NT <= 2) {
+    if (run_job(a, dyn_lds)) return;
+  }
   constexpr int KW = 4 * NV;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int rho = lane & 15;      // row of each interleaved tile / B-operand column
   const int g = lane >> 4;        // reduction element group
 
-  int bid = blockIdx.x;
+  int bid = (int)blockIdx.x - a.job_on;
   const int rg = bid % a.n_rg; bid /= a.n_rg;
   const int mg = bid % a.n_mg; bid /= a.n_mg;
   const int lb = bid;
@@ -696,9 +718,19 @@ __global__ __launch_bounds__(256) void frag_quant_kernel(const float* __restrict
   }
 }
 
+// Grid and LDS of a launch: the contraction's, plus the job's workgroup (and
+// at least its LDS) when one rides along.
+inline void with_job(const KArgs& a, int64_t& grid, size_t& lds) {
+  if (a.job_on) {
+    grid += 1;
+    lds = std::max(lds, factor_gj_lds_bytes(a.job.R));
+  }
+}
+
 template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
 hipError_t launch_one(const KArgs& a, int64_t grid, hipStream_t st) {
-  const size_t lds = ((size_t)a.loop_block * a.R + (a.wr > 1 ? 4 * NT * 4 * 64 : 0)) * sizeof(float);
+  size_t lds = ((size_t)a.loop_block * a.R + (a.wr > 1 ? 4 * NT * 4 * 64 : 0)) * sizeof(float);
+  with_job(a, grid, lds);
   hipLaunchKernelGGL((contract_kernel<PREC, NT, NV, CONTIG, VEC>), dim3((unsigned)grid), dim3(256), lds, st, a);
   return hipGetLastError();
 }
@@ -736,8 +768,10 @@ template <int PREC, int NT>
 hipError_t launch_cm(const KArgs& a, const ContractPlan& p, hipStream_t st) {
   constexpr int NV = 8;
   if (p.nv != NV) return hipErrorInvalidValue;
-  const size_t lds = ((size_t)a.loop_block * a.R + (a.wr > 1 ? 4 * 16 * NT * 64 : 0)) * sizeof(float);
-  hipLaunchKernelGGL((contract_cm_kernel<PREC, NT, NV>), dim3((unsigned)p.grid()), dim3(256), lds, st, a);
+  size_t lds = ((size_t)a.loop_block * a.R + (a.wr > 1 ? 4 * 16 * NT * 64 : 0)) * sizeof(float);
+  int64_t grid = p.grid();
+  with_job(a, grid, lds);
+  hipLaunchKernelGGL((contract_cm_kernel<PREC, NT, NV>), dim3((unsigned)grid), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
@@ -886,8 +920,11 @@ size_t contract_ws_bytes(const ContractPlan& p, int prec) {
 
 hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void* X,
                            const int32_t* slice_exp, const float* frag_src, const float* weight,
-                           float* out, void* ws, hipStream_t st) {
+                           float* out, void* ws, hipStream_t st, const FactorArgs* job) {
+  if (job && (job->R > kJobMaxRank || p.ntw > 2)) return hipErrorInvalidValue;
   KArgs a{};
+  a.job_on = job ? 1 : 0;
+  if (job) a.job = *job;
   a.X = X;
   a.slice_exp = slice_exp;
   a.frag_src = frag_src;

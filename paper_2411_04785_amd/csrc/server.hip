@@ -228,6 +228,14 @@ struct mtk_server {
         const float* fr = n == 2 ? f[1] : f[2];
         const float* wt = n == 0 ? f[1] : f[0];
         mtk::ContractPlan p = mtk::make_plan(r.dims, R, n, r.prec, true);
+        if (R <= mtk::kJobMaxRank) {
+          const mtk::FactorArgs job = mtk::factor_args(r.dims, R, n, maxdim, solve_ws, s.d_status);
+          if ((e = mtk::launch_contract(p, r.prec, n, X, nullptr, fr, wt, M, scratch, s.st, &job)) != hipSuccess)
+            return e;
+          if ((e = mtk::launch_apply(r.dims, R, n, M, f[n], lam, maxdim, solve_ws, s.d_status, s.st)) != hipSuccess)
+            return e;
+          continue;
+        }
         if ((e = mtk::launch_contract(p, r.prec, n, X, nullptr, fr, wt, M, scratch, s.st)) != hipSuccess) return e;
         if ((e = mtk::launch_update(r.dims, R, n, M, f[n], lam, maxdim, solve_ws, s.d_status, s.st)) != hipSuccess)
           return e;
