@@ -132,6 +132,30 @@ mtk_status mtk_quantize_fp8(mtk_ctx* ctx, const float* x, const int64_t dims[3],
 mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
                   int64_t R, int mode, int prec, float* out, void* stream);
 
+/* Mode-0 or mode-1 MTTKRP by the dimension tree, the form als_sweep uses
+ * for those two updates when mtk_sweep_uses_dimtree says so.  First
+ * Y = X x_3 C, Y(i,j,r) = sum_k X(i,j,k) C(k,r) (an I*J x R FP32
+ * intermediate in the context's workspace, one pass over X), then
+ *     mode 0:  M(i,r) = sum_j Y(i,j,r) B(j,r)
+ *     mode 1:  M(j,r) = sum_i Y(i,j,r) A(i,r)
+ * which is the mttkrp result with its sums associated differently (equal up
+ * to rounding).  Deterministic, and bitwise equal to the MTTKRP of the same
+ * mode inside an als_sweep that uses the tree.
+ *  X     : FP32 tensor, prec MTK_FP32 or MTK_BF16X3 (arithmetic of the
+ *          contraction with C; the sums over Y are FP32).
+ *  mode  : 0 or 1.  factors[2] and factors[1 - mode] are read.
+ *  R, out, stream : as for mttkrp.
+ * MTK_EUNSUPPORTED if dims[0]*dims[1] > 2^36. */
+mtk_status mttkrp_dimtree(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
+                          int64_t R, int mode, int prec, float* out, void* stream);
+
+/* 1 if als_sweep forms the mode-0 and mode-1 MTTKRPs of each sweep of this
+ * shape, rank and precision by the dimension tree (two passes over X per
+ * sweep instead of three), else 0.  Currently: FP32 tensors (MTK_FP32,
+ * MTK_BF16X3) with dims[2] >= 8 R, where writing and twice reading Y costs
+ * well under the pass it saves. */
+int mtk_sweep_uses_dimtree(const int64_t dims[3], int64_t R, int prec);
+
 /* Normal-equation update of one factor (FP64 on the device).
  *  V = *_{m != mode} A_m^T A_m  (R x R, FP64, from the FP32 factors)
  *  V^{-1} by symmetric elimination: the LDL^T (square-root-free Cholesky)
@@ -156,7 +180,8 @@ mtk_status gram_solve(mtk_ctx* ctx, const float* const factors[3], const int64_t
 mtk_status mtk_fit(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
                    const double* lambda, int64_t R, double* fit_host, void* stream);
 
-/* CP-ALS sweeps.  Each sweep updates modes 0, 1, 2 in order: mttkrp, then
+/* CP-ALS sweeps.  Each sweep updates modes 0, 1, 2 in order: mttkrp (for
+ * modes 0 and 1 mttkrp_dimtree when mtk_sweep_uses_dimtree), then
  * gram_solve in place into factors[mode] and lambda.  The factors given are
  * used as the starting point (not normalised first); lambda (device FP64[R])
  * is overwritten.  Calling again with the same buffers continues the

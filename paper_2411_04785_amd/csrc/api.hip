@@ -60,10 +60,13 @@ bool dims_ok(const int64_t d[3]) {
 
 mtk_status ensure_ws(mtk_ctx* c, size_t bytes, hipStream_t st) {
   if (bytes <= c->ws_bytes) return MTK_OK;
-  // The old workspace may still be in use by queued work.
+  // The old workspace may still be in use by queued work, and every cached
+  // sweep graph holds its address.
   if (c->ws) {
     HIP_OR_FAIL(c, hipStreamSynchronize(st));
     HIP_OR_FAIL(c, hipDeviceSynchronize());
+    mtk_status gs = mtk_graph_reset(c);
+    if (gs != MTK_OK) return gs;
     HIP_OR_FAIL(c, hipFree(c->ws));
     c->ws = nullptr;
     c->ws_bytes = 0;
@@ -116,9 +119,12 @@ size_t sweep_contract_bytes(const int64_t dims[3], int R, int prec) {
   return round256(std::max(b, mtk::fit_ws_bytes(dims)));
 }
 
+// ... followed by the dimension-tree region (Y and its partial sums) when
+// the sweep uses one.
 size_t sweep_scratch_bytes(const int64_t dims[3], int R, int prec) {
   const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
-  return sweep_contract_bytes(dims, R, prec) + mtk::solve_ws_bytes(maxdim, R);
+  const size_t dt = mtk::dimtree_used(dims, R, prec) ? mtk::dimtree_ws_bytes(dims, R) : 0;
+  return sweep_contract_bytes(dims, R, prec) + mtk::solve_ws_bytes(maxdim, R) + dt;
 }
 
 }  // namespace
@@ -268,6 +274,32 @@ mtk_status mttkrp(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3]
   return mttkrp_impl(c, X, factors, (int)R, mode, prec, out, c->ws, st);
 }
 
+mtk_status mttkrp_dimtree(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], int64_t R, int mode,
+                          int prec, float* out, void* stream) {
+  if (!c) return MTK_EINVAL;
+  mtk_status s = check_tensor(c, X);
+  if (s != MTK_OK) return s;
+  if ((s = check_prec(c, X, prec)) != MTK_OK) return s;
+  if (X->fmt != MTK_FP32) return fail(c, MTK_EINVAL, "mttkrp_dimtree takes an FP32 tensor (prec MTK_FP32 or MTK_BF16X3)");
+  if (mode != 0 && mode != 1) return fail(c, MTK_EINVAL, "mttkrp_dimtree: mode must be 0 or 1");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  if (!factors || !out || !factors[2] || !factors[1 - mode]) return fail(c, MTK_EINVAL, "NULL factors or out");
+  if (X->dims[0] * X->dims[1] > mtk::kDimtreeMaxRows)
+    return fail(c, MTK_EUNSUPPORTED, "mttkrp_dimtree: dims[0]*dims[1] above 2^36");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = ensure_ws(c, mtk::dimtree_ws_bytes(X->dims, (int)R), st)) != MTK_OK) return s;
+  hipError_t e = mtk::launch_dimtree_mttkrp(mode, true, static_cast<const float*>(X->data), aligned16(X->data),
+                                            X->dims, factors, (int)R, prec, out, c->ws, st, nullptr);
+  if (e != hipSuccess) return hip_fail(c, e, "dimension-tree launch");
+  return MTK_OK;
+}
+
+int mtk_sweep_uses_dimtree(const int64_t dims[3], int64_t R, int prec) {
+  if (!dims || !dims_ok(dims) || R < 1 || R > mtk::kMaxRank) return 0;
+  return mtk::dimtree_used(dims, (int)R, prec) ? 1 : 0;
+}
+
 mtk_status gram_solve(mtk_ctx* c, const float* const factors[3], const int64_t dims[3], int64_t R, int mode,
                       const float* M, float* factor_out, double* lambda_out, void* stream) {
   if (!c) return MTK_EINVAL;
@@ -321,6 +353,26 @@ static void* sweep_solve_ws(mtk_ctx* c, const int64_t dims[3], int R, int prec) 
   return scratch + sweep_contract_bytes(dims, R, prec);
 }
 
+static void* sweep_dimtree_ws(mtk_ctx* c, const int64_t dims[3], int R, int prec) {
+  if (!mtk::dimtree_used(dims, R, prec)) return nullptr;
+  const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
+  return static_cast<char*>(sweep_solve_ws(c, dims, R, prec)) + mtk::solve_ws_bytes(maxdim, R);
+}
+
+// The mode-n MTTKRP of a sweep: modes 0 and 1 from the dimension tree when
+// the sweep uses one (dt_ws != nullptr), otherwise the direct contraction.
+static mtk_status sweep_mttkrp(mtk_ctx* c, const mtk_tensor* X, const float* const cf[3], int R, int n, int prec,
+                               float* M, void* scratch, void* dt_ws, hipStream_t st,
+                               const mtk::FactorArgs* job = nullptr) {
+  if (dt_ws && n < 2) {
+    hipError_t e = mtk::launch_dimtree_mttkrp(n, n == 0, static_cast<const float*>(X->data), aligned16(X->data),
+                                              X->dims, cf, R, prec, M, dt_ws, st, job);
+    if (e != hipSuccess) return hip_fail(c, e, "dimension-tree launch");
+    return MTK_OK;
+  }
+  return mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st, job);
+}
+
 static mtk_status enqueue_initial_grams(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], int R, int prec,
                                         hipStream_t st) {
   const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
@@ -343,19 +395,20 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
   float* M = static_cast<float*>(c->ws);
   void* scratch = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
   void* solve_ws = sweep_solve_ws(c, X->dims, R, prec);
+  void* dt_ws = sweep_dimtree_ws(c, X->dims, R, prec);
   const float* cf[3] = {factors[0], factors[1], factors[2]};
   const bool overlap = R >= kOverlapMinRank;
   for (int n = 0; n < 3; ++n) {
     if (R <= mtk::kJobMaxRank) {
       const mtk::FactorArgs f = mtk::factor_args(X->dims, R, n, maxdim, solve_ws, c->d_status);
-      mtk_status s = mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st, &f);
+      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st, &f);
       if (s != MTK_OK) return s;
       hipError_t e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st);
       if (e != hipSuccess) return hip_fail(c, e, "update launch");
       continue;
     }
     if (!overlap) {
-      mtk_status s = mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st);
+      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st);
       if (s != MTK_OK) return s;
       hipError_t e = mtk::launch_update(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st);
       if (e != hipSuccess) return hip_fail(c, e, "update launch");
@@ -366,7 +419,7 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
     hipError_t e = mtk::launch_factor(X->dims, R, n, maxdim, solve_ws, c->d_status, c->side);
     if (e != hipSuccess) return hip_fail(c, e, "factorisation launch");
     HIP_OR_FAIL(c, hipEventRecord(c->join_ev[n], c->side));
-    mtk_status s = mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st);
+    mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st);
     if (s != MTK_OK) return s;
     HIP_OR_FAIL(c, hipStreamWaitEvent(st, c->join_ev[n], 0));
     e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st);
@@ -392,11 +445,7 @@ mtk_status als_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], d
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
   const size_t need = round256((size_t)maxdim * R * sizeof(float)) + sweep_scratch_bytes(X->dims, (int)R, prec);
-  if (c->ws_bytes < need) {
-    // A graph bakes in the workspace address: growing it invalidates them.
-    mtk_graph_reset(c);
-    if ((s = ensure_ws(c, need, st)) != MTK_OK) return s;
-  }
+  if ((s = ensure_ws(c, need, st)) != MTK_OK) return s;   // growing it drops the cached graphs
   if (nsweeps == 0) return mtk_check(c, stream);
 
   const bool with_fit = fit_host != nullptr;

@@ -72,6 +72,22 @@ hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void
                            const int32_t* slice_exp, const float* frag_src,
                            const float* weight, float* out, void* ws, hipStream_t st,
                            const FactorArgs* job = nullptr);
+// out[e] = sum over s in order of part[s * n + e], e < n.
+hipError_t launch_slice_reduce(const float* part, int slices, int64_t n, float* out, hipStream_t st);
+
+// Dimension-tree sweep (dimtree.hip): the mode-0 and mode-1 MTTKRPs from
+// Y = X x3 C (I*J x R, at the start of `ws`).  form_y: form Y first; else Y
+// must still be in ws from an earlier call on the same stream with the same
+// X and C (the mode-1 update of a sweep reuses the mode-0 update's Y).
+// FP32 / BF16X3, FP32 tensor.  `ws`: dimtree_ws_bytes.  `job` (R <=
+// kJobMaxRank) rides in the mode-0 Y launch or the mode-1 sum.
+// Largest dims[0]*dims[1] (rows of Y) the tree takes.
+constexpr int64_t kDimtreeMaxRows = (int64_t)1 << 36;
+bool dimtree_used(const int64_t dims[3], int R, int prec);
+size_t dimtree_ws_bytes(const int64_t dims[3], int R);
+hipError_t launch_dimtree_mttkrp(int mode, bool form_y, const float* X, bool x_aligned16, const int64_t dims[3],
+                                 const float* const factors[3], int R, int prec, float* out, void* ws,
+                                 hipStream_t st, const FactorArgs* job);
 
 // FP8 tensor preparation (per mode-1 slice power-of-two scaled e4m3).
 hipError_t launch_quantize_slices(const float* x, int64_t I, int64_t J, int64_t K, uint8_t* q,

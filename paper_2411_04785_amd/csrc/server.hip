@@ -152,10 +152,12 @@ size_t contract_region_bytes(const int64_t dims[3], int R, int prec) {
 }
 
 // The solve region (which keeps the Gram matrices across the MTTKRPs)
-// follows the contraction region.
+// follows the contraction region, then the dimension-tree region when the
+// sweep uses one.
 size_t scratch_bytes(const int64_t dims[3], int R, int prec) {
   const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
-  return contract_region_bytes(dims, R, prec) + mtk::solve_ws_bytes(maxdim, R);
+  const size_t dt = mtk::dimtree_used(dims, R, prec) ? mtk::dimtree_ws_bytes(dims, R) : 0;
+  return contract_region_bytes(dims, R, prec) + mtk::solve_ws_bytes(maxdim, R) + dt;
 }
 
 size_t device_bytes(const int64_t dims[3], int R, int prec) {
@@ -223,22 +225,26 @@ struct mtk_server {
     void* solve_ws = static_cast<char*>(scratch) + contract_region_bytes(r.dims, R, r.prec);
     if (r.sweeps > 0 && (e = mtk::launch_grams(cf, r.dims, R, 1, 2, maxdim, solve_ws, s.d_status, s.st)) != hipSuccess)
       return e;
+    // The same kernels in the same order as a lone als_sweep of this request.
+    void* dt_ws = mtk::dimtree_used(r.dims, R, r.prec)
+                      ? static_cast<char*>(solve_ws) + mtk::solve_ws_bytes(maxdim, R)
+                      : nullptr;
     for (int sw = 0; sw < r.sweeps; ++sw) {
       for (int n = 0; n < 3; ++n) {
-        const float* fr = n == 2 ? f[1] : f[2];
-        const float* wt = n == 0 ? f[1] : f[0];
-        mtk::ContractPlan p = mtk::make_plan(r.dims, R, n, r.prec, true);
-        if (R <= mtk::kJobMaxRank) {
-          const mtk::FactorArgs job = mtk::factor_args(r.dims, R, n, maxdim, solve_ws, s.d_status);
-          if ((e = mtk::launch_contract(p, r.prec, n, X, nullptr, fr, wt, M, scratch, s.st, &job)) != hipSuccess)
-            return e;
-          if ((e = mtk::launch_apply(r.dims, R, n, M, f[n], lam, maxdim, solve_ws, s.d_status, s.st)) != hipSuccess)
-            return e;
-          continue;
+        const mtk::FactorArgs job = mtk::factor_args(r.dims, R, n, maxdim, solve_ws, s.d_status);
+        const mtk::FactorArgs* jp = R <= mtk::kJobMaxRank ? &job : nullptr;
+        if (dt_ws && n < 2) {
+          e = mtk::launch_dimtree_mttkrp(n, n == 0, X, true, r.dims, cf, R, r.prec, M, dt_ws, s.st, jp);
+        } else {
+          const float* fr = n == 2 ? f[1] : f[2];
+          const float* wt = n == 0 ? f[1] : f[0];
+          mtk::ContractPlan p = mtk::make_plan(r.dims, R, n, r.prec, true);
+          e = mtk::launch_contract(p, r.prec, n, X, nullptr, fr, wt, M, scratch, s.st, jp);
         }
-        if ((e = mtk::launch_contract(p, r.prec, n, X, nullptr, fr, wt, M, scratch, s.st)) != hipSuccess) return e;
-        if ((e = mtk::launch_update(r.dims, R, n, M, f[n], lam, maxdim, solve_ws, s.d_status, s.st)) != hipSuccess)
-          return e;
+        if (e != hipSuccess) return e;
+        e = jp ? mtk::launch_apply(r.dims, R, n, M, f[n], lam, maxdim, solve_ws, s.d_status, s.st)
+               : mtk::launch_update(r.dims, R, n, M, f[n], lam, maxdim, solve_ws, s.d_status, s.st);
+        if (e != hipSuccess) return e;
       }
     }
     if ((e = mtk::launch_fit(X, MTK_FP32, nullptr, r.dims, cf, lam, R, s.d_fit, scratch, s.st)) != hipSuccess)

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "MTK_OK", -1: "MTK_EINVAL", -2: "MTK_ENOMEM", -3: "MTK_EHIP",
                 -5: "MTK_EUNSUPPORTED", -6: "MTK_EBUDGET", -7: "MTK_EAGAIN"}
 
 EXPORTED = ["mtk_create", "mtk_destroy", "mtk_last_error", "mtk_check", "mtk_reserve",
-            "mtk_quantize_fp8", "mttkrp", "gram_solve", "mtk_fit", "als_sweep", "mtk_graph_reset",
+            "mtk_quantize_fp8", "mttkrp", "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
+            "als_sweep", "mtk_graph_reset",
             "mtk_server_create", "mtk_server_submit", "mtk_server_poll", "mtk_server_stats",
             "mtk_server_destroy"]
 
@@ -73,6 +74,8 @@ def lib() -> ctypes.CDLL:
         "mtk_reserve": (i32, [vp, ctypes.POINTER(i64), i64, i32]),
         "mtk_quantize_fp8": (i32, [vp, vp, ctypes.POINTER(i64), vp, vp, vp, vp]),
         "mttkrp": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
+        "mttkrp_dimtree": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
+        "mtk_sweep_uses_dimtree": (i32, [ctypes.POINTER(i64), i64, i32]),
         "gram_solve": (i32, [vp, P3, ctypes.POINTER(i64), i64, i32, vp, vp, vp, vp]),
         "mtk_fit": (i32, [vp, ctypes.POINTER(Tensor), P3, vp, i64, ctypes.POINTER(d), vp]),
         "als_sweep": (i32, [vp, ctypes.POINTER(Tensor), P3, vp, i64, i32, i32, ctypes.POINTER(d), vp]),
@@ -191,6 +194,23 @@ class Context:
         self._chk(self._L.mttkrp(self.h, ctypes.byref(d), fp, R, int(mode), _prec(prec), _ptr(out),
                                  _stream(stream)))
         return out
+
+    def mttkrp_dimtree(self, X, factors, mode: int, prec="fp32", out=None, R=None, stream=None):
+        """Mode-0 / mode-1 MTTKRP through Y = X x3 C (the sweep's dimension tree)."""
+        import torch
+        R = int(R if R is not None else next(f for f in factors if f is not None).shape[1])
+        d = self.tensor_desc(X)
+        if out is None:
+            rows = d.dims[mode] if 0 <= int(mode) < 3 else 1     # invalid modes are rejected by the library
+            out = torch.empty((rows, R), dtype=torch.float32, device=X.device)
+        fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
+        self._chk(self._L.mttkrp_dimtree(self.h, ctypes.byref(d), fp, R, int(mode), _prec(prec), _ptr(out),
+                                         _stream(stream)))
+        return out
+
+    @staticmethod
+    def sweep_uses_dimtree(dims, R: int, prec="fp32") -> bool:
+        return bool(lib().mtk_sweep_uses_dimtree(_dims(dims), int(R), _prec(prec)))
 
     def gram_solve(self, factors, dims, mode: int, M, factor_out=None, lambda_out=None, R=None, stream=None):
         import torch

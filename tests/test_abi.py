@@ -42,3 +42,15 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.mtk_create(None, 0) == b.MTK_EINVAL
     assert L.mtk_destroy(None) == b.MTK_OK
     assert L.mtk_last_error(None) == b"NULL context"
+
+
+def test_dimtree_choice_without_gpu():
+    # Host-only query: the sweep forms Y = X x3 C for FP32 / bf16x3 when K >= 8 R.
+    from paper_2411_04785_amd.mttkrp import Context
+    assert Context.sweep_uses_dimtree((512, 512, 512), 32, "fp32")
+    assert Context.sweep_uses_dimtree((1024, 1024, 1024), 64, "bf16x3")
+    assert Context.sweep_uses_dimtree((40, 36, 32), 4, "fp32")
+    assert not Context.sweep_uses_dimtree((40, 36, 31), 4, "fp32")
+    assert not Context.sweep_uses_dimtree((768, 768, 768), 128, "fp8")
+    assert not Context.sweep_uses_dimtree((512, 512, 512), 0, "fp32")
+    assert not Context.sweep_uses_dimtree((512, 512, 512), 129, "fp32")

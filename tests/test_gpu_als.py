@@ -125,22 +125,54 @@ def test_als_resume_bitwise(ctx):
         assert np.array_equal(host(x), host(y))
 
 
-def test_graph_replay_equals_eager(ctx):
-    # One captured sweep == the same calls made one by one, bitwise.
+@pytest.mark.parametrize("dims,R", [((40, 36, 24), 4), ((40, 36, 32), 4), ((50, 45, 400), 40)])
+def test_graph_replay_equals_eager(ctx, dims, R):
+    # One captured sweep == the same calls made one by one, bitwise: modes 0
+    # and 1 by mttkrp_dimtree where the sweep uses the dimension tree.
     import torch
     from gpu_util import dev, host
-    w, X, facs = _small(seed=55)
+    from paper_2411_04785_amd.mttkrp import Context
+    w, X, facs = _small(dims=dims, rank=R, R=R, seed=55)
+    tree = Context.sweep_uses_dimtree(dims, R, "bf16x3")
+    assert tree == (dims[2] >= 8 * R)
     Xd = dev(X)
     g = [dev(f) for f in facs]
-    lg = dev(np.ones(4))
+    lg = dev(np.ones(R))
     for _ in range(3):                           # replays after the first capture
         ctx.als_sweep(Xd, g, lg, 1, "bf16x3")
     e = [dev(f) for f in facs]
-    le = dev(np.ones(4))
+    le = dev(np.ones(R))
     for _ in range(3):
         for mode in range(3):
-            M = ctx.mttkrp(Xd, e, mode, "bf16x3")
+            if tree and mode < 2:
+                M = ctx.mttkrp_dimtree(Xd, e, mode, "bf16x3")
+            else:
+                M = ctx.mttkrp(Xd, e, mode, "bf16x3")
             ctx.gram_solve(e, w.dims, mode, M, factor_out=e[mode], lambda_out=le)
-        torch.cuda.synchronize()
+        ctx.check()
     for x, y in zip(g + [lg], e + [le]):
         assert np.array_equal(host(x), host(y))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("dims,R", [((70, 45, 200), 20), ((33, 40, 330), 40)])
+def test_dimtree_sweeps_match_oracle(ctx, prec, dims, R):
+    # Sweeps whose first two updates come from Y = X x3 C (ragged row tiles
+    # and C chunks; R = 20 carries the inversion inside the Y launches).
+    from gpu_util import dev, host, rel
+    from paper_2411_04785_amd.mttkrp import Context
+    assert Context.sweep_uses_dimtree(dims, R, prec)
+    w, X, facs = _small(dims=dims, rank=R, R=R, noise=1e-4, seed=77)
+    fd = [dev(f) for f in facs]
+    lam = dev(np.ones(R))
+    Xd = dev(X)
+    ctx.als_sweep(Xd, fd, lam, 1, prec)
+    of, ol, _ = oracle.cp_als(X, facs, 1)
+    # One sweep: the MTTKRP bars (1e-5) times the conditioning of the three
+    # normal-equation solves.
+    assert rel(host(lam), ol) <= 1e-4
+    for a, b in zip(fd, of):
+        assert rel(host(a), b) <= 1e-4
+    fits = ctx.als_sweep(Xd, fd, lam, 5, prec, with_fit=True)
+    _, _, ofits = oracle.cp_als(X, facs, 6)
+    assert np.all(np.abs(fits - np.asarray(ofits[1:])) <= 1e-4), (fits, ofits)

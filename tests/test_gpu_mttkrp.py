@@ -189,3 +189,46 @@ def test_abi_errors(ctx):
         ctx.mttkrp(Xd, [fd[0], None, fd[2]], 0, "fp32")
     ok = ctx.mttkrp(Xd, [None, fd[1], fd[2]], 0, "fp32")   # factors[mode] may be NULL
     assert ok.shape == (8, 4)
+
+
+DIMTREE = [
+    ((1, 1, 1), 1),
+    ((37, 50, 29), 5),
+    ((3, 200, 7), 20),
+    ((130, 17, 300), 37),
+    ((33, 65, 129), 64),
+    ((20, 24, 260), 128),
+    ((64, 96, 128), 16),
+    ((5, 7, 1000), 33),
+    ((70, 30, 131), 32),
+    ((9, 11, 66), 8),
+    ((16, 16, 64), 80),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("dims,R", DIMTREE)
+def test_dimtree_matches_oracle(ctx, prec, dims, R):
+    # Y = X x3 C (row tiles x LDS chunks of C, ragged in both), then the
+    # sums over Y for modes 0 and 1.
+    from gpu_util import dev, host, rel
+    X, facs = _case(dims, R, seed=sum(dims) + R)
+    Xd, fd = dev(X), [dev(f) for f in facs]
+    for mode in (1, 0):            # each call forms its own Y
+        _say("dimtree", prec, dims, R, mode)
+        got = host(ctx.mttkrp_dimtree(Xd, fd, mode, prec))
+        ctx.check()
+        ref = oracle.mttkrp(X, facs, mode)
+        assert rel(got, ref) <= TOL[prec], (mode, rel(got, ref))
+
+
+def test_dimtree_deterministic_and_rejects(ctx):
+    from gpu_util import dev, host
+    from paper_2411_04785_amd.mttkrp import MtkError
+    X, facs = _case((45, 38, 150), 24, seed=3)
+    Xd, fd = dev(X), [dev(f) for f in facs]
+    a = host(ctx.mttkrp_dimtree(Xd, fd, 1, "fp32"))
+    b = host(ctx.mttkrp_dimtree(Xd, fd, 1, "fp32"))
+    assert np.array_equal(a, b)
+    with pytest.raises(MtkError):
+        ctx.mttkrp_dimtree(Xd, fd, 2, "fp32")
