@@ -4,8 +4,10 @@
 Default workload (N=1): 512 x 512 x 512 FP32 tensor, rank-32 CP model plus
 N(0, 1e-4) noise, R = 32 factors iid N(0,1) (synthetic, seeded).  One step =
 one CP-ALS sweep on the device: for each mode an MTTKRP (HIP contraction +
-fixed-order split-K reduce) followed by the FP64 Gram / LDL^T (Cholesky)
-inverse / solve / normalise update.  ``value`` is algorithmic MTTKRP GFLOP/s of the whole
+fixed-order split-K reduce; for FP32 tensors with K >= 8R the mode-1 and mode-2
+MTTKRPs come from one shared contraction Y = X x3 C, the dimension tree, so
+the sweep reads X twice) followed by the FP64 Gram / LDL^T (Cholesky) inverse /
+solve / normalise update.  ``value`` is algorithmic MTTKRP GFLOP/s of the whole
 sweep (3 * 2*I*J*K*R flop per step over the step time, solves included).
 
 Also measured live (HIP events on the library's stream): each mode's MTTKRP
@@ -338,7 +340,8 @@ def main():
                    "mttkrp_gflops": [round(flop_mttkrp / (t * 1e-3) / 1e9, 1) for t in mode_ms],
                    "mttkrp_gbs": [round(b / (t * 1e-3) / 1e9, 1) for b, t in zip(bytes_modes, mode_ms)],
                    "roofline_us_hbm": round(t_hbm * 1e6, 2), "roofline_us_compute": round(t_cmp * 1e6, 2),
-                   "err_rel_sampled_rows": [float(f"{e:.3e}") for e in errs], "fit_after": round(fit, 7)},
+                   "err_rel_sampled_rows": [float(f"{e:.3e}") for e in errs], "fit_after": round(fit, 7),
+                   "sweep_passes_over_X": 2 if Context.sweep_uses_dimtree(w.dims, R, prec) else 3},
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -194,6 +194,28 @@ mtk_status als_sweep(mtk_ctx* ctx, const mtk_tensor* X, float* const factors[3],
                      double* lambda, int64_t R, int prec, int nsweeps, double* fit_host,
                      void* stream);
 
+/* CP-ALS until the fit settles: up to max_sweeps sweeps (the same captured
+ * sweep as als_sweep, so k sweeps here leave the factors bitwise equal to
+ * als_sweep with nsweeps = k), stopping after the first sweep s >= 1 whose
+ * fit differs from sweep s-1's by less than tol (tol = 0: run all).
+ * The per-sweep fit costs no pass over X: at the least-squares solution of
+ * the sweep's last update F = M V^{-1} (before normalising),
+ * ||Xhat||^2 = <X, Xhat> = <F, M>, so
+ *     fit = 1 - sqrt(max(0, ||X||^2 - <F, M>)) / ||X||
+ * with <F, M> accumulated in FP64 by the update and ||X||^2 formed once per
+ * call (one pass over X).  Its absolute error is about
+ * e ||X|| / (2 ||X - Xhat||) for a relative MTTKRP error e (1e-7 FP32), so
+ * it is a monitor, not the reported fit, at fits close to 1.
+ *  fits_host   : host double[max_sweeps] or NULL; receives the per-sweep fits.
+ *  sweeps_done : host int, sweeps run.
+ *  fit_final   : host double or NULL; the direct-residual fit (as mtk_fit) of
+ *                the final model.
+ * Synchronises `stream` once per sweep.  Returns the sticky status; a
+ * sweep that sets MTK_ENOTSPD ends the run. */
+mtk_status als_run(mtk_ctx* ctx, const mtk_tensor* X, float* const factors[3], double* lambda,
+                   int64_t R, int prec, int max_sweeps, double tol, double* fits_host,
+                   int* sweeps_done, double* fit_final, void* stream);
+
 /* Drop every cached als_sweep graph of this context. */
 mtk_status mtk_graph_reset(mtk_ctx* ctx);
 

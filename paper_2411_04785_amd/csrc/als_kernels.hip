@@ -113,7 +113,8 @@ __global__ __launch_bounds__(256) void gj_inv_kernel(FactorArgs f) {
 // row block's sums of F^2 per column (rows in a fixed order).
 __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M, int64_t n, int R,
                                                     const double* __restrict__ Vinv, const int* __restrict__ status,
-                                                    double* __restrict__ F, double* __restrict__ colsq) {
+                                                    double* __restrict__ F, double* __restrict__ colsq,
+                                                    double* __restrict__ ipsum) {
   if (*status & kStatusNotSPD) return;
   __shared__ double Vs[kMaxRank * 16];
   __shared__ float Ms[kApplyRows][kMaxRank + 1];
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
 #pragma unroll
     for (int m = 0; m < 4; ++m) acc[m] = fma((double)Ms[g + 16 * m][k], v, acc[m]);
   }
-  double s = 0.0;
+  double s = 0.0, ip = 0.0;
   const int col = cb + c;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -146,6 +147,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
     if (q < n && col < R) {
       F[q * R + col] = acc[m];
       s = fma(acc[m], acc[m], s);
+      ip = fma(acc[m], (double)Ms[g + 16 * m][col], ip);
     }
   }
   red[g][c] = s;
@@ -155,6 +157,17 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
 #pragma unroll
     for (int gg = 0; gg < 16; ++gg) t += red[gg][tid];
     colsq[(int64_t)blockIdx.x * R + cb + tid] = t;
+  }
+  if (ipsum) {                       // <F, M> of this block, per column (same order as colsq)
+    __syncthreads();
+    red[g][c] = ip;
+    __syncthreads();
+    if (tid < 16 && cb + tid < R) {
+      double t = 0.0;
+#pragma unroll
+      for (int gg = 0; gg < 16; ++gg) t += red[gg][tid];
+      ipsum[(int64_t)blockIdx.x * R + cb + tid] = t;
+    }
   }
 }
 
@@ -166,13 +179,28 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
 __global__ __launch_bounds__(256) void normalize_gram_kernel(const double* __restrict__ F, int64_t n, int R,
                                                              const double* __restrict__ colsq, int nblk,
                                                              const int* __restrict__ status, double* __restrict__ lam,
-                                                             float* __restrict__ out, double* __restrict__ part) {
+                                                             float* __restrict__ out, double* __restrict__ part,
+                                                             const double* __restrict__ ipsum, double* __restrict__ ip) {
   if (*status & kStatusNotSPD) return;
   __shared__ double lsum[8][32];
   __shared__ double lt[32];
+  __shared__ double ired[256];
   int tr, ts;
   tile_pair(blockIdx.x, tr, ts);
   const int tid = threadIdx.x;
+  if (ipsum && blockIdx.x == 0 && blockIdx.y == 0) {
+    // <F, M> over the whole factor: strided per-thread sums, then a tree, in
+    // fixed order.
+    double t = 0.0;
+    for (int64_t e = tid; e < (int64_t)nblk * R; e += 256) t += ipsum[e];
+    ired[tid] = t;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) ired[tid] += ired[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) *ip = ired[0];
+  }
   const bool diag = tr == ts;
   {
     // Column u of the tile pair (u < 16: tr, else ts): thread (q, u) sums
@@ -225,6 +253,8 @@ struct SolveWs {
   double* Vinv;
   double* F;
   double* colsq;
+  double* ipsum;      // per row block and column: <F, M> (mode-3 update of a sweep)
+  double* ip;         // their total
 };
 
 SolveWs solve_ws(int64_t maxdim, int R, void* ws) {
@@ -235,6 +265,8 @@ SolveWs solve_ws(int64_t maxdim, int R, void* ws) {
   w.Vinv = reinterpret_cast<double*>(take(p, (size_t)R * R * sizeof(double)));
   w.F = reinterpret_cast<double*>(take(p, md * R * sizeof(double)));
   w.colsq = reinterpret_cast<double*>(take(p, (size_t)cdiv((int64_t)md, kApplyRows) * R * sizeof(double)));
+  w.ipsum = reinterpret_cast<double*>(take(p, (size_t)cdiv((int64_t)md, kApplyRows) * R * sizeof(double)));
+  w.ip = reinterpret_cast<double*>(take(p, sizeof(double)));
   return w;
 }
 }  // namespace
@@ -245,9 +277,12 @@ size_t solve_ws_bytes(int64_t maxdim, int R) {
   size_t b = 3 * r256(gram_part_elems(R) * sizeof(double));
   b += r256((size_t)R * R * sizeof(double));
   b += r256(md * R * sizeof(double));
-  b += r256((size_t)cdiv((int64_t)md, kApplyRows) * R * sizeof(double));
+  b += 2 * r256((size_t)cdiv((int64_t)md, kApplyRows) * R * sizeof(double));
+  b += 256;
   return b;
 }
+
+const double* solve_ip(int64_t maxdim, int R, void* ws) { return solve_ws(maxdim, R, ws).ip; }
 
 hipError_t launch_grams(const float* const factors[3], const int64_t dims[3], int R, int ma, int mb, int64_t maxdim,
                         void* ws, int* status, hipStream_t st) {
@@ -293,22 +328,23 @@ hipError_t launch_factor(const int64_t dims[3], int R, int mode, int64_t maxdim,
 }
 
 hipError_t launch_apply(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
-                        int64_t maxdim, void* ws, int* status, hipStream_t st) {
+                        int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip) {
   const int64_t n = dims[mode];
   SolveWs w = solve_ws(maxdim, R, ws);
   const int nblk = (int)cdiv(n, kApplyRows);
   hipLaunchKernelGGL(apply_kernel, dim3(nblk, (R + 15) / 16), dim3(256), 0, st, M, n, R, w.Vinv, status, w.F,
-                     w.colsq);
+                     w.colsq, with_ip ? w.ipsum : nullptr);
   hipLaunchKernelGGL(normalize_gram_kernel, dim3(gram_pairs(R), gram_blocks(n, R)), dim3(256), 0, st, w.F, n, R, w.colsq,
-                     nblk, status, lambda, factor_out, w.part[mode]);
+                     nblk, status, lambda, factor_out, w.part[mode], with_ip ? w.ipsum : nullptr,
+                     with_ip ? w.ip : nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_update(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
-                         int64_t maxdim, void* ws, int* status, hipStream_t st) {
+                         int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip) {
   hipError_t e = launch_factor(dims, R, mode, maxdim, ws, status, st);
   if (e != hipSuccess) return e;
-  return launch_apply(dims, R, mode, M, factor_out, lambda, maxdim, ws, status, st);
+  return launch_apply(dims, R, mode, M, factor_out, lambda, maxdim, ws, status, st, with_ip);
 }
 
 hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3], int R, int mode,
@@ -330,6 +366,14 @@ hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3
 // order final sum.
 // ---------------------------------------------------------------------------
 namespace {
+
+// Value of an e4m3 code (NaN for 0x7F / 0xFF).
+__device__ inline double e4m3_to_double(uint8_t c) {
+  const int e = (c >> 3) & 15, mnt = c & 7;
+  double v = e == 0 ? ldexp((double)mnt, -9) : ldexp(1.0 + mnt / 8.0, e - 7);
+  if ((c & 0x7f) == 0x7f) v = __builtin_nan("");
+  return (c & 0x80) ? -v : v;
+}
 
 __global__ __launch_bounds__(256) void fit_partial_kernel(const void* __restrict__ X, int fmt,
                                                           const int32_t* __restrict__ slice_exp,
@@ -358,11 +402,7 @@ __global__ __launch_bounds__(256) void fit_partial_kernel(const void* __restrict
       double x;
       const int64_t off = (i * J + j) * K + k;
       if (fmt == MTK_FP8_E4M3) {
-        const uint8_t c = static_cast<const uint8_t*>(X)[off];
-        const int e = (c >> 3) & 15, mnt = c & 7;
-        double v = e == 0 ? ldexp((double)mnt, -9) : ldexp(1.0 + mnt / 8.0, e - 7);
-        if ((c & 0x7f) == 0x7f) v = __builtin_nan("");
-        x = ((c & 0x80) ? -v : v) * sc;
+        x = e4m3_to_double(static_cast<const uint8_t*>(X)[off]) * sc;
       } else {
         x = (double)static_cast<const float*>(X)[off];
       }
@@ -416,6 +456,44 @@ hipError_t launch_fit(const void* X, int fmt, const int32_t* slice_exp, const in
   hipLaunchKernelGGL(fit_partial_kernel, dim3((unsigned)cdiv(dims[1], 16), (unsigned)dims[0]), dim3(256), 0,
                      st, X, fmt, slice_exp, dims[0], dims[1], dims[2], factors[0], factors[1], factors[2],
                      lambda, R, part);
+  hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(256), 0, st, part, nb, acc2);
+  return hipGetLastError();
+}
+
+namespace {
+// ||X||^2 partials (FP64): block b sums elements b, b + nb, ... of its
+// grid-stride share in order and writes the pair (0, sum) for fit_final_kernel.
+__global__ __launch_bounds__(256) void sumsq_kernel(const void* __restrict__ X, int fmt,
+                                                    const int32_t* __restrict__ slice_exp, int64_t n, int64_t slice,
+                                                    double* __restrict__ part) {
+  double t = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    double x;
+    if (fmt == MTK_FP8_E4M3) x = e4m3_to_double(static_cast<const uint8_t*>(X)[e]) * ldexp(1.0, slice_exp[e / slice]);
+    else x = (double)static_cast<const float*>(X)[e];
+    t = fma(x, x, t);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = 0.0;
+    part[2 * blockIdx.x + 1] = red[0];
+  }
+}
+}  // namespace
+
+hipError_t launch_sumsq(const void* X, int fmt, const int32_t* slice_exp, const int64_t dims[3], double* acc2,
+                        void* ws, hipStream_t st) {
+  double* part = static_cast<double*>(ws);
+  const int64_t n = dims[0] * dims[1] * dims[2];
+  // fit_ws_bytes holds at least dims[0] pairs; 1024 blocks at most.
+  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>({1024, dims[0], cdiv(n, 256)}));
+  hipLaunchKernelGGL(sumsq_kernel, dim3((unsigned)nb), dim3(256), 0, st, X, fmt, slice_exp, n, dims[1] * dims[2], part);
   hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(256), 0, st, part, nb, acc2);
   return hipGetLastError();
 }

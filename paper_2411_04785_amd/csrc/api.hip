@@ -403,14 +403,16 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
       const mtk::FactorArgs f = mtk::factor_args(X->dims, R, n, maxdim, solve_ws, c->d_status);
       mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st, &f);
       if (s != MTK_OK) return s;
-      hipError_t e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st);
+      hipError_t e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st,
+                                       n == 2);
       if (e != hipSuccess) return hip_fail(c, e, "update launch");
       continue;
     }
     if (!overlap) {
       mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st);
       if (s != MTK_OK) return s;
-      hipError_t e = mtk::launch_update(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st);
+      hipError_t e = mtk::launch_update(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st,
+                                        n == 2);
       if (e != hipSuccess) return hip_fail(c, e, "update launch");
       continue;
     }
@@ -422,13 +424,53 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
     mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st);
     if (s != MTK_OK) return s;
     HIP_OR_FAIL(c, hipStreamWaitEvent(st, c->join_ev[n], 0));
-    e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st);
+    e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st, n == 2);
     if (e != hipSuccess) return hip_fail(c, e, "update launch");
   }
   if (with_fit) {
     hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, R, c->d_fit, scratch, st);
     if (e != hipSuccess) return hip_fail(c, e, "fit launch");
   }
+  return MTK_OK;
+}
+
+// The captured sweep for these buffers (created and cached on first use).
+static mtk_status sweep_graph(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int R,
+                              int prec, bool with_fit, hipGraphExec_t* out) {
+  GraphCache* gc = static_cast<GraphCache*>(c->graph_cache);
+  GraphKey key{};
+  key.X = X->data;
+  key.Xt = X->data_t;
+  for (int m = 0; m < 3; ++m) { key.dims[m] = X->dims[m]; key.f[m] = factors[m]; }
+  key.fmt = X->fmt;
+  key.slice_exp = X->slice_exp;
+  key.lambda = lambda;
+  key.R = R;
+  key.prec = prec;
+  key.with_fit = with_fit;
+  auto it = gc->execs.find(key);
+  if (it != gc->execs.end()) {
+    *out = it->second;
+    return MTK_OK;
+  }
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIP_OR_FAIL(c, hipStreamBeginCapture(gc->capture_stream, hipStreamCaptureModeThreadLocal));
+  mtk_status s = enqueue_sweep(c, X, factors, lambda, R, prec, with_fit, gc->capture_stream);
+  hipError_t ee = hipStreamEndCapture(gc->capture_stream, &g);
+  if (s != MTK_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (ee != hipSuccess) return hip_fail(c, ee, "hipStreamEndCapture");
+  ee = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  if (ee != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(c, ee, "hipGraphInstantiate");
+  }
+  gc->graphs.push_back(g);
+  gc->execs[key] = exec;
+  *out = exec;
   return MTK_OK;
 }
 
@@ -449,39 +491,8 @@ mtk_status als_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], d
   if (nsweeps == 0) return mtk_check(c, stream);
 
   const bool with_fit = fit_host != nullptr;
-  GraphCache* gc = static_cast<GraphCache*>(c->graph_cache);
-  GraphKey key{};
-  key.X = X->data;
-  key.Xt = X->data_t;
-  for (int m = 0; m < 3; ++m) { key.dims[m] = X->dims[m]; key.f[m] = factors[m]; }
-  key.fmt = X->fmt;
-  key.slice_exp = X->slice_exp;
-  key.lambda = lambda;
-  key.R = (int)R;
-  key.prec = prec;
-  key.with_fit = with_fit;
   hipGraphExec_t exec = nullptr;
-  auto it = gc->execs.find(key);
-  if (it != gc->execs.end()) {
-    exec = it->second;
-  } else {
-    hipGraph_t g = nullptr;
-    HIP_OR_FAIL(c, hipStreamBeginCapture(gc->capture_stream, hipStreamCaptureModeThreadLocal));
-    s = enqueue_sweep(c, X, factors, lambda, (int)R, prec, with_fit, gc->capture_stream);
-    hipError_t ee = hipStreamEndCapture(gc->capture_stream, &g);
-    if (s != MTK_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return s;
-    }
-    if (ee != hipSuccess) return hip_fail(c, ee, "hipStreamEndCapture");
-    ee = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-    if (ee != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      return hip_fail(c, ee, "hipGraphInstantiate");
-    }
-    gc->graphs.push_back(g);
-    gc->execs[key] = exec;
-  }
+  if ((s = sweep_graph(c, X, factors, lambda, (int)R, prec, with_fit, &exec)) != MTK_OK) return s;
   // The Gram matrices the first mode needs; every later one is formed by the
   // update that writes its factor.
   if ((s = enqueue_initial_grams(c, X, factors, (int)R, prec, st)) != MTK_OK) return s;
@@ -495,6 +506,63 @@ mtk_status als_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], d
   if (with_fit)
     for (int sw = 0; sw < nsweeps; ++sw) fit_host[sw] = 1.0 - std::sqrt(acc[2 * sw]) / std::sqrt(acc[2 * sw + 1]);
   return s;
+}
+
+mtk_status als_run(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int64_t R, int prec,
+                   int max_sweeps, double tol, double* fits_host, int* sweeps_done, double* fit_final, void* stream) {
+  if (!c) return MTK_EINVAL;
+  mtk_status s = check_tensor(c, X);
+  if (s != MTK_OK) return s;
+  if ((s = check_prec(c, X, prec)) != MTK_OK) return s;
+  if (!factors || !factors[0] || !factors[1] || !factors[2] || !lambda || !sweeps_done)
+    return fail(c, MTK_EINVAL, "NULL argument");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  if (max_sweeps < 0) return fail(c, MTK_EINVAL, "max_sweeps < 0");
+  if (!(tol >= 0.0)) return fail(c, MTK_EINVAL, "tol must be >= 0");
+  *sweeps_done = 0;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
+  const size_t need = round256((size_t)maxdim * R * sizeof(float)) + sweep_scratch_bytes(X->dims, (int)R, prec);
+  if ((s = ensure_ws(c, need, st)) != MTK_OK) return s;
+  void* scratch = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
+  const float* cf[3] = {factors[0], factors[1], factors[2]};
+  if (max_sweeps > 0) {
+    hipGraphExec_t exec = nullptr;
+    if ((s = sweep_graph(c, X, factors, lambda, (int)R, prec, false, &exec)) != MTK_OK) return s;
+    double acc[2] = {0.0, 0.0};
+    hipError_t e = mtk::launch_sumsq(X->data, X->fmt, X->slice_exp, X->dims, c->d_fit, scratch, st);
+    if (e != hipSuccess) return hip_fail(c, e, "norm launch");
+    HIP_OR_FAIL(c, hipMemcpyAsync(acc, c->d_fit, sizeof(acc), hipMemcpyDeviceToHost, st));
+    if ((s = enqueue_initial_grams(c, X, factors, (int)R, prec, st)) != MTK_OK) return s;
+    const double* ip_dev = mtk::solve_ip(maxdim, (int)R, sweep_solve_ws(c, X->dims, (int)R, prec));
+    const double nx2 = acc[1];
+    double prev = 0.0;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+      HIP_OR_FAIL(c, hipGraphLaunch(exec, st));
+      double ip = 0.0;
+      int status = 0;
+      HIP_OR_FAIL(c, hipMemcpyAsync(&ip, ip_dev, sizeof(ip), hipMemcpyDeviceToHost, st));
+      HIP_OR_FAIL(c, hipMemcpyAsync(&status, c->d_status, sizeof(status), hipMemcpyDeviceToHost, st));
+      HIP_OR_FAIL(c, hipStreamSynchronize(st));
+      *sweeps_done = sw + 1;
+      if (status != 0) break;                    // reported by mtk_check below
+      // At the least-squares solution of the last update, ||Xhat||^2 = <X, Xhat> = <F, M>.
+      const double fit = 1.0 - std::sqrt(std::max(0.0, nx2 - ip)) / std::sqrt(nx2);
+      if (fits_host) fits_host[sw] = fit;
+      if (sw > 0 && std::fabs(fit - prev) < tol) break;
+      prev = fit;
+    }
+  }
+  if (fit_final) {
+    double acc[2] = {0.0, 0.0};
+    hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, (int)R, c->d_fit, scratch, st);
+    if (e != hipSuccess) return hip_fail(c, e, "fit launch");
+    HIP_OR_FAIL(c, hipMemcpyAsync(acc, c->d_fit, sizeof(acc), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(c, hipStreamSynchronize(st));
+    *fit_final = 1.0 - std::sqrt(acc[0]) / std::sqrt(acc[1]);
+  }
+  return mtk_check(c, stream);
 }
 
 }  // extern "C"

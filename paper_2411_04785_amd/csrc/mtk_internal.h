@@ -108,8 +108,11 @@ hipError_t launch_grams(const float* const factors[3], const int64_t dims[3], in
 // other factors: V^{-1} (LDL^T elimination in Gauss-Jordan form),
 // F = M V^{-1}, lambda, the normalised FP32 factor, and the Gram slot of the
 // new factor.
+// with_ip: also form <F, M> (F = M V^{-1} before normalising) into the solve
+// region's scalar (solve_ip); used by the last update of a sweep, where
+// ||X||^2 - <F, M> is the squared residual of the updated model.
 hipError_t launch_update(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
-                         int64_t maxdim, void* ws, int* status, hipStream_t st);
+                         int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip = false);
 // launch_update in two halves: the factorisation (V^{-1} by LDL^T /
 // Gauss-Jordan elimination; reads only the Gram slots of the other two
 // factors, so it may run concurrently with the mode's MTTKRP) and the rest
@@ -118,7 +121,9 @@ FactorArgs factor_args(const int64_t dims[3], int R, int mode, int64_t maxdim, v
 hipError_t launch_factor(const int64_t dims[3], int R, int mode, int64_t maxdim, void* ws, int* status,
                          hipStream_t st);
 hipError_t launch_apply(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
-                        int64_t maxdim, void* ws, int* status, hipStream_t st);
+                        int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip = false);
+// Device address of the <F, M> scalar in a solve region laid out for maxdim.
+const double* solve_ip(int64_t maxdim, int R, void* ws);
 // launch_grams of the two other factors followed by launch_update.
 hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3], int R,
                              int mode, const float* M, float* factor_out, double* lambda,
@@ -127,6 +132,9 @@ size_t fit_ws_bytes(const int64_t dims[3]);
 hipError_t launch_fit(const void* X, int fmt, const int32_t* slice_exp, const int64_t dims[3],
                       const float* const factors[3], const double* lambda, int R,
                       double* acc2 /* [2]: residual^2, norm^2 */, void* ws, hipStream_t st);
+// acc2[1] = ||X||^2 (FP64; acc2[0] = 0); ws: fit_ws_bytes.
+hipError_t launch_sumsq(const void* X, int fmt, const int32_t* slice_exp, const int64_t dims[3], double* acc2,
+                        void* ws, hipStream_t st);
 
 }  // namespace mtk
 

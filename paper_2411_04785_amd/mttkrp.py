@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "MTK_OK", -1: "MTK_EINVAL", -2: "MTK_ENOMEM", -3: "MTK_EHIP",
 
 EXPORTED = ["mtk_create", "mtk_destroy", "mtk_last_error", "mtk_check", "mtk_reserve",
             "mtk_quantize_fp8", "mttkrp", "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
-            "als_sweep", "mtk_graph_reset",
+            "als_sweep", "als_run", "mtk_graph_reset",
             "mtk_server_create", "mtk_server_submit", "mtk_server_poll", "mtk_server_stats",
             "mtk_server_destroy"]
 
@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
         "gram_solve": (i32, [vp, P3, ctypes.POINTER(i64), i64, i32, vp, vp, vp, vp]),
         "mtk_fit": (i32, [vp, ctypes.POINTER(Tensor), P3, vp, i64, ctypes.POINTER(d), vp]),
         "als_sweep": (i32, [vp, ctypes.POINTER(Tensor), P3, vp, i64, i32, i32, ctypes.POINTER(d), vp]),
+        "als_run": (i32, [vp, ctypes.POINTER(Tensor), P3, vp, i64, i32, i32, d, ctypes.POINTER(d),
+                          ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
         "mtk_graph_reset": (i32, [vp]),
         "mtk_server_create": (i32, [ctypes.POINTER(vp), i32, ctypes.c_uint64, i32]),
         "mtk_server_submit": (i32, [vp, i64, vp, ctypes.POINTER(i64), i64, i32, i32, P3, P3, vp]),
@@ -243,6 +245,21 @@ class Context:
         self._chk(self._L.als_sweep(self.h, ctypes.byref(d), fp, _ptr(lam), int(factors[0].shape[1]),
                                     _prec(prec), int(nsweeps), fptr, _stream(stream)))
         return fits[:nsweeps] if with_fit else None
+
+    def als_run(self, X, factors, lam, max_sweeps: int, prec="fp32", tol: float = 0.0, slice_exp=None,
+                final_fit=True, stream=None, X_t=None):
+        """CP-ALS until the per-sweep fit changes by less than tol (at most
+        max_sweeps).  Returns (per-sweep fits, sweeps run, direct fit of the
+        final model or None)."""
+        d = self.tensor_desc(X, slice_exp, X_t=X_t)
+        fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
+        fits = np.zeros(max(1, max_sweeps))
+        done = ctypes.c_int(0)
+        ff = ctypes.c_double(float("nan"))
+        self._chk(self._L.als_run(self.h, ctypes.byref(d), fp, _ptr(lam), int(factors[0].shape[1]), _prec(prec),
+                                  int(max_sweeps), float(tol), fits.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.byref(done), ctypes.byref(ff) if final_fit else None, _stream(stream)))
+        return fits[:done.value], done.value, (ff.value if final_fit else None)
 
     def graph_reset(self):
         self._chk(self._L.mtk_graph_reset(self.h))

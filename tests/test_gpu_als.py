@@ -176,3 +176,59 @@ def test_dimtree_sweeps_match_oracle(ctx, prec, dims, R):
     fits = ctx.als_sweep(Xd, fd, lam, 5, prec, with_fit=True)
     _, _, ofits = oracle.cp_als(X, facs, 6)
     assert np.all(np.abs(fits - np.asarray(ofits[1:])) <= 1e-4), (fits, ofits)
+
+
+def test_als_run_fits_and_replay(ctx):
+    # Per-sweep fits from the last update's <F, M> against the oracle's
+    # direct fits; k sweeps of als_run == als_sweep(k), bitwise; the final
+    # direct fit equals mtk_fit.
+    from gpu_util import dev, host
+    w, X, facs = _small(dims=(60, 50, 40), rank=5, R=5, noise=1e-2, seed=91)
+    Xd = dev(X)
+    a = [dev(f) for f in facs]
+    la = dev(np.ones(5))
+    fits, done, ffin = ctx.als_run(Xd, a, la, 6, "fp32", tol=0.0)
+    assert done == 6
+    _, _, ofits = oracle.cp_als(X, facs, 6)
+    # The transient-fit bar of the sweep tests (FP32 vs FP64 trajectories).
+    assert np.all(np.abs(fits - np.asarray(ofits)) <= 1e-4), (fits, ofits)
+    b = [dev(f) for f in facs]
+    lb = dev(np.ones(5))
+    ctx.als_sweep(Xd, b, lb, 6, "fp32")
+    for x, y in zip(a + [la], b + [lb]):
+        assert np.array_equal(host(x), host(y))
+    assert ffin == ctx.fit(Xd, a, la)
+    assert abs(ffin - ofits[-1]) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_als_run_stops_when_fit_settles(ctx, prec):
+    from gpu_util import dev
+    w, X, facs = _small(dims=(48, 40, 64), rank=4, R=4, noise=1e-3, seed=92)
+    fd = [dev(f) for f in facs]
+    lam = dev(np.ones(4))
+    tol = 1e-4
+    fits, done, ffin = ctx.als_run(dev(X), fd, lam, 60, prec, tol=tol)
+    assert 2 <= done < 60
+    d = np.abs(np.diff(fits))
+    assert d[-1] < tol and np.all(d[:-1] >= tol)
+    # Monitor vs direct residual: e ||X|| / (2 ||X - Xhat||) for MTTKRP error e.
+    assert abs(ffin - fits[-1]) <= (1e-4 if prec == "fp32" else 5e-4)
+    _, _, ofits = oracle.cp_als(X, facs, done)
+    assert abs(ffin - ofits[-1]) <= 1e-4
+
+
+def test_als_run_fp8_and_arguments(ctx):
+    import torch
+    from gpu_util import dev
+    from paper_2411_04785_amd.mttkrp import MtkError
+    w, X, facs = _small(dims=(32, 30, 28), rank=3, R=3, noise=1e-2, seed=93)
+    q, ex, qt = ctx.quantize_fp8(dev(X), transposed=True)
+    fd = [dev(f) for f in facs]
+    lam = dev(np.ones(3))
+    fits, done, ffin = ctx.als_run(q, fd, lam, 4, "fp8", slice_exp=ex, X_t=qt)
+    assert done == 4 and np.all(np.isfinite(fits)) and 0.0 < ffin <= 1.0
+    with pytest.raises(MtkError):
+        ctx.als_run(dev(X), fd, lam, 2, "fp32", tol=-1.0)
+    fits, done, ffin = ctx.als_run(dev(X), fd, lam, 0, "fp32")
+    assert done == 0 and len(fits) == 0 and 0.0 < ffin <= 1.0

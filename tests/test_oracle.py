@@ -181,6 +181,28 @@ def test_fit_matches_expansion_when_well_conditioned():
     assert abs(oracle.fit(X, facs, lam) - (1 - res / np.linalg.norm(X))) < 1e-12
 
 
+def test_fit_from_last_update_inner_product():
+    # After a least-squares update of the last factor, F = M V^{-1} (before
+    # normalising) satisfies ||Xhat||^2 = <X, Xhat> = <F, M>, so the squared
+    # residual is ||X||^2 - <F, M> (the per-sweep fit the sweep kernels form).
+    X, facs = rand_case((7, 8, 9), 4, seed=73)
+    X = X + np.einsum("ir,jr,kr->ijk", *facs)
+    facs = [f + 0.2 * np.random.default_rng(9 + m).standard_normal(f.shape) for m, f in enumerate(facs)]
+    M = oracle.mttkrp(X, facs, 2)
+    V = oracle.gram_hadamard(facs, 2)
+    F = np.linalg.solve(V, M.T).T
+    C, lam = oracle.normalize_columns(F)
+    direct = oracle.fit(X, [facs[0], facs[1], C], lam)
+    nx2 = float((X * X).sum())
+    expansion = 1.0 - np.sqrt(nx2 - float((F * M).sum())) / np.sqrt(nx2)
+    assert abs(direct - expansion) < 1e-12
+    # It is not an identity away from the solution (a wrong update fails it).
+    F2 = 1.01 * F
+    C2, lam2 = oracle.normalize_columns(F2)
+    assert abs(oracle.fit(X, [facs[0], facs[1], C2], lam2)
+               - (1.0 - np.sqrt(nx2 - float((F2 * M).sum())) / np.sqrt(nx2))) > 1e-6
+
+
 def test_als_fixed_point_exact_cp():
     X, facs = exact_cp((6, 7, 8), 3, seed=81)
     f, lam, fits = oracle.cp_als(X, facs, sweeps=1)
