@@ -56,7 +56,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         if rc != 0:
             raise RuntimeError(f"hipcc failed on {s}")
     tmp = OUT + ".tmp"
-    rc, out = _run([HIPCC, *COMMON, "-shared", *objs, "-o", tmp, "-lpthread"])
+    rc, out = _run([HIPCC, *COMMON, "-shared", *objs, "-o", tmp, "-lpthread", "-Wl,--no-undefined"])
     if rc != 0:
         print(out, file=sys.stderr)
         raise RuntimeError("link failed")
