@@ -375,6 +375,18 @@ __device__ inline double e4m3_to_double(uint8_t c) {
   return (c & 0x80) ? -v : v;
 }
 
+typedef __attribute__((ext_vector_type(4))) double d4;
+
+// Squared residual and squared norm of X against the CP model, FP64.  For
+// slice i the model block Xhat(j, k) = sum_r W(j, r) C(k, r), W(j, r) =
+// lambda_r A(i, r) B(j, r), is a product of shape (16 j) x R x (16 k) per
+// tile, done on FP64 MFMA (16x16x4): wave w of the workgroup owns JT tiles
+// of 16 j and walks the k tiles; lane (n, g) holds W(j0 + n, 4s + g) as its
+// A operand and C(k0 + n, 4s + g) as its B operand for step s, and receives
+// Xhat(j0 + g + 4v, k0 + n), v = 0..3 (the FP64 result layout, measured on
+// the device; the FP32 16x16x4 one is rows 4g + v).  Partial sums per
+// workgroup in fixed order.
+template <int RQ, int JT>
 __global__ __launch_bounds__(256) void fit_partial_kernel(const void* __restrict__ X, int fmt,
                                                           const int32_t* __restrict__ slice_exp,
                                                           int64_t I, int64_t J, int64_t K,
@@ -383,44 +395,82 @@ __global__ __launch_bounds__(256) void fit_partial_kernel(const void* __restrict
                                                           const double* __restrict__ lam, int R,
                                                           double* __restrict__ part) {
   const int64_t i = blockIdx.y;
-  const int64_t jb = blockIdx.x;
-  const int jj = threadIdx.x >> 4, kk = threadIdx.x & 15;
-  const int64_t j = jb * 16 + jj;
-  __shared__ double w[16][kMaxRank];           // lambda_r A(i,r) B(j,r) for the 16 rows
-  for (int e = threadIdx.x; e < 16 * R; e += 256) {
-    const int q = e / R, r = e % R;
-    const int64_t jq = jb * 16 + q;
-    w[q][r] = jq < J ? lam[r] * (double)A[i * R + r] * (double)B[jq * R + r] : 0.0;
-  }
-  __syncthreads();
-  double res = 0.0, nrm = 0.0;
-  if (j < J) {
-    const double sc = fmt == MTK_FP8_E4M3 ? ldexp(1.0, slice_exp[i]) : 1.0;
-    for (int64_t k = kk; k < K; k += 16) {
-      double model = 0.0;
-      for (int r = 0; r < R; ++r) model = fma(w[jj][r], (double)C[k * R + r], model);
-      double x;
-      const int64_t off = (i * J + j) * K + k;
-      if (fmt == MTK_FP8_E4M3) {
-        x = e4m3_to_double(static_cast<const uint8_t*>(X)[off]) * sc;
-      } else {
-        x = (double)static_cast<const float*>(X)[off];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 15, g = lane >> 4;
+  const int64_t jw = ((int64_t)blockIdx.x * 4 + wave) * (16 * JT);   // first j of this wave
+  double w[JT][RQ];
+#pragma unroll
+  for (int t = 0; t < JT; ++t)
+#pragma unroll
+    for (int s = 0; s < RQ; ++s) {
+      const int r = 4 * s + g;
+      const int64_t j = jw + 16 * t + n;
+      w[t][s] = (r < R && j < J) ? lam[r] * (double)A[i * R + r] * (double)B[j * R + r] : 0.0;
+    }
+  const double sc = fmt == MTK_FP8_E4M3 ? ldexp(1.0, slice_exp[i]) : 1.0;
+  // The k tile's C operands and X values are loaded one tile ahead.
+  float cq[RQ], xq[JT][4];
+  auto load = [&](int64_t k0) {
+    const int64_t kc = k0 + n;
+    const bool k_ok = kc < K;
+#pragma unroll
+    for (int s = 0; s < RQ; ++s) {
+      const int r = 4 * s + g;
+      cq[s] = C[(k_ok ? kc : 0) * R + (r < R ? r : 0)];
+    }
+#pragma unroll
+    for (int t = 0; t < JT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = jw + 16 * t + g + 4 * v;
+        const bool ok = j < J && k_ok;
+        const int64_t off = ok ? (i * J + j) * K + kc : 0;
+        xq[t][v] = fmt == MTK_FP8_E4M3 ? (float)static_cast<const uint8_t*>(X)[off]
+                                       : static_cast<const float*>(X)[off];
       }
-      const double d = x - model;
-      res = fma(d, d, res);
-      nrm = fma(x, x, nrm);
+  };
+  double res = 0.0, nrm = 0.0;
+  load(0);
+  for (int64_t k0 = 0; k0 < K; k0 += 16) {
+    const int64_t kc = k0 + n;
+    const bool k_ok = kc < K;
+    double cb[RQ];
+#pragma unroll
+    for (int s = 0; s < RQ; ++s) cb[s] = (k_ok && 4 * s + g < R) ? (double)cq[s] : 0.0;
+    double xv[JT][4];
+#pragma unroll
+    for (int t = 0; t < JT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        xv[t][v] = fmt == MTK_FP8_E4M3 ? e4m3_to_double((uint8_t)xq[t][v]) * sc : (double)xq[t][v];
+    if (k0 + 16 < K) load(k0 + 16);
+#pragma unroll
+    for (int t = 0; t < JT; ++t) {
+      d4 m = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < RQ; ++s) m = __builtin_amdgcn_mfma_f64_16x16x4f64(w[t][s], cb[s], m, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = jw + 16 * t + g + 4 * v;
+        if (j < J && k_ok) {
+          const double x = xv[t][v];
+          const double d = x - m[v];
+          res = fma(d, d, res);
+          nrm = fma(x, x, nrm);
+        }
+      }
     }
   }
   __shared__ double sr[256], sn[256];
   sr[threadIdx.x] = res;
   sn[threadIdx.x] = nrm;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) { sr[threadIdx.x] += sr[threadIdx.x + s]; sn[threadIdx.x] += sn[threadIdx.x + s]; }
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) { sr[threadIdx.x] += sr[threadIdx.x + h]; sn[threadIdx.x] += sn[threadIdx.x + h]; }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int64_t b = i * gridDim.x + jb;
+    const int64_t b = i * gridDim.x + blockIdx.x;
     part[2 * b] = sr[0];
     part[2 * b + 1] = sn[0];
   }
@@ -452,11 +502,24 @@ hipError_t launch_fit(const void* X, int fmt, const int32_t* slice_exp, const in
                       const float* const factors[3], const double* lambda, int R, double* acc2, void* ws,
                       hipStream_t st) {
   double* part = static_cast<double*>(ws);
-  const int64_t nb = dims[0] * cdiv(dims[1], 16);
-  hipLaunchKernelGGL(fit_partial_kernel, dim3((unsigned)cdiv(dims[1], 16), (unsigned)dims[0]), dim3(256), 0,
-                     st, X, fmt, slice_exp, dims[0], dims[1], dims[2], factors[0], factors[1], factors[2],
-                     lambda, R, part);
-  hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(256), 0, st, part, nb, acc2);
+  // MFMA steps RQ = R/4 rounded up to a power of two; two j tiles per wave
+  // while the model operands fit in registers.
+  const int rq = R <= 8 ? 2 : R <= 16 ? 4 : R <= 32 ? 8 : R <= 64 ? 16 : 32;
+  const int jt = rq <= 16 ? 2 : 1;
+  const int64_t nbx = cdiv(dims[1], 64 * jt);
+  const dim3 grid((unsigned)nbx, (unsigned)dims[0]);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, X, fmt, slice_exp, dims[0], dims[1], dims[2], factors[0],
+                       factors[1], factors[2], lambda, R, part);
+  };
+  switch (rq) {
+    case 2: go(fit_partial_kernel<2, 2>); break;
+    case 4: go(fit_partial_kernel<4, 2>); break;
+    case 8: go(fit_partial_kernel<8, 2>); break;
+    case 16: go(fit_partial_kernel<16, 2>); break;
+    default: go(fit_partial_kernel<32, 1>); break;
+  }
+  hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(256), 0, st, part, dims[0] * nbx, acc2);
   return hipGetLastError();
 }
 
