@@ -232,3 +232,18 @@ def test_als_run_fp8_and_arguments(ctx):
         ctx.als_run(dev(X), fd, lam, 2, "fp32", tol=-1.0)
     fits, done, ffin = ctx.als_run(dev(X), fd, lam, 0, "fp32")
     assert done == 0 and len(fits) == 0 and 0.0 < ffin <= 1.0
+
+
+def test_als_run_stops_on_singular_update(ctx):
+    # A zero column in B and C makes the first update's V singular: the run
+    # ends after that sweep and reports MTK_ENOTSPD; the status is cleared.
+    from gpu_util import dev
+    from paper_2411_04785_amd.mttkrp import NotSPDError
+    w, X, facs = _small(dims=(40, 36, 320), rank=4, R=20, seed=94)
+    facs = [f.copy() for f in facs]
+    facs[1][:, 3] = 0.0
+    facs[2][:, 3] = 0.0
+    fd = [dev(f) for f in facs]
+    with pytest.raises(NotSPDError):
+        ctx.als_run(dev(X), fd, dev(np.ones(20)), 10, "fp32", tol=0.0, final_fit=False)
+    ctx.check()

@@ -102,3 +102,26 @@ def test_failing_request_leaves_others_unchanged():
         assert got[q]["status"] == 0
         f, lam = _alone(X, init, "fp32", 3)
         assert all(np.array_equal(a, b) for a, b in zip(got[q]["factors"], f))
+
+
+def test_mix_equals_alone_large_rank_dimension_tree():
+    # R > 32 (no inversion riding in the Y launch) and K >= 8R (the sweep uses
+    # the dimension tree), next to requests that do not use it.
+    from paper_2411_04785_amd.mttkrp import Context, Server
+    reqs = []
+    for q, (dims, R) in enumerate((((40, 36, 320), 40), ((33, 30, 400), 48), ((50, 45, 60), 40), ((30, 28, 64), 8))):
+        w = synth.Workload(f"t{q}", dims, min(R, 8), R, 1e-4, 2000 + q)
+        reqs.append((q, synth.tensor(w, threads=2), synth.init_factors(w)))
+    assert Context.sweep_uses_dimtree((40, 36, 320), 40, "fp32")
+    assert not Context.sweep_uses_dimtree((50, 45, 60), 40, "fp32")
+    srv = Server(0, budget_bytes=2 * 10**9, max_slots=4)
+    for q, X, init in reqs:
+        srv.submit(q, X, init, "fp32", sweeps=3)
+    got = _drain(srv, len(reqs))
+    srv.close()
+    for q, X, init in reqs:
+        assert got[q]["status"] == 0
+        f, lam = _alone(X, init, "fp32", 3)
+        for a, b in zip(got[q]["factors"], f):
+            assert np.array_equal(a, b), q
+        assert np.array_equal(got[q]["lambda"], lam), q
