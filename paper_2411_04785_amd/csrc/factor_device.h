@@ -89,7 +89,9 @@ __device__ inline void gather_v(const FactorArgs& f, int Rp, double* A, int ld) 
 //   A(i,j) <- A(i,j) - A(i,k) A(k,j) / p          (i, j != k),
 // after which A holds V^{-1}.  The owners of row k and column k publish
 // them (start-of-step values) in a double-buffered LDS slot, so each step
-// needs one barrier.  Padding rows/columns (identity) pass through.
+// needs one barrier.  A slot holds element ti*B + u at u*16 + ti, so the 16
+// column blocks of a wave read consecutive doubles (no bank conflicts).
+// Padding rows/columns (identity) pass through.
 template <int B, bool LEAN = false>
 __device__ inline void factor_gj(const FactorArgs& f, double* lds) {
   constexpr int RP = 16 * B;
@@ -118,21 +120,21 @@ __device__ inline void factor_gj(const FactorArgs& f, double* lds) {
       const int buf = k & 1;
       if (tj == kb) {
 #pragma unroll
-        for (int u = 0; u < B; ++u) bc[(2 * buf) * RP + i0 + u] = a[u][kk];
+        for (int u = 0; u < B; ++u) bc[(2 * buf) * RP + u * 16 + ti] = a[u][kk];
       }
       if (ti == kb) {
 #pragma unroll
-        for (int v = 0; v < B; ++v) bc[(2 * buf + 1) * RP + j0 + v] = a[kk][v];
+        for (int v = 0; v < B; ++v) bc[(2 * buf + 1) * RP + v * 16 + tj] = a[kk][v];
       }
       __syncthreads();
-      const double p = bc[(2 * buf) * RP + k];
+      const double p = bc[(2 * buf) * RP + kk * 16 + kb];
       bad |= !(p > 0.0);                           // uniform: every thread reads the same p
       const double r = 1.0 / p;
       double ci[B], rj[B];
 #pragma unroll
-      for (int u = 0; u < B; ++u) ci[u] = bc[(2 * buf) * RP + i0 + u] * r;
+      for (int u = 0; u < B; ++u) ci[u] = bc[(2 * buf) * RP + u * 16 + ti] * r;
 #pragma unroll
-      for (int v = 0; v < B; ++v) rj[v] = bc[(2 * buf + 1) * RP + j0 + v];
+      for (int v = 0; v < B; ++v) rj[v] = bc[(2 * buf + 1) * RP + v * 16 + tj];
 #pragma unroll
       for (int u = 0; u < B; ++u)
 #pragma unroll

@@ -57,7 +57,7 @@ def test_gram_solve_many_row_blocks(ctx):
         assert rel(host(f_out), An) <= 1e-6
 
 
-@pytest.mark.parametrize("R", [4, 24, 40])
+@pytest.mark.parametrize("R", [4, 24, 40, 64])
 def test_gram_solve_not_spd(ctx, R):
     # One factorisation path each: register-resident R <= 16, R <= 32, blocked.
     from gpu_util import dev
