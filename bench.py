@@ -299,13 +299,18 @@ def main():
 
     # Sampled parity of the timed results against the FP64 oracle.
     rng = np.random.default_rng(0)
-    errs = []
+    errs, worst = [], []
+    mags = synth.slice_magnitudes(w)
     for mode in range(3):
-        rows = np.unique(np.concatenate([[0, w.dims[mode] - 1], rng.integers(0, w.dims[mode], 6)]))
+        rows = [0, w.dims[mode] - 1]
+        if mode == 0 and mags is not None:          # the smallest and largest slices
+            rows += [int(np.argmin(mags)), int(np.argmax(mags))]
+        rows = np.unique(np.concatenate([rows, rng.integers(0, w.dims[mode], 6)]))
         ref = oracle.mttkrp_rows(X, facs, mode, rows)
         got = outs[mode][rows].astype(np.float64)
         errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
-    log(f"[bench] sampled relative error vs FP64 oracle per mode: {errs}")
+        worst.append(float(np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1))))
+    log(f"[bench] sampled relative error vs FP64 oracle per mode: {errs} (worst row {worst})")
 
     # ---- timed CP-ALS sweeps ----
     fd = [f.clone() for f in f0]
@@ -364,7 +369,8 @@ def main():
                    "mttkrp_gflops": [round(flop_mttkrp / (t * 1e-3) / 1e9, 1) for t in mode_ms],
                    "mttkrp_gbs": [round(b / (t * 1e-3) / 1e9, 1) for b, t in zip(bytes_modes, mode_ms)],
                    "roofline_us_hbm": round(t_hbm * 1e6, 2), "roofline_us_compute": round(t_cmp * 1e6, 2),
-                   "err_rel_sampled_rows": [float(f"{e:.3e}") for e in errs], "fit_after": round(fit, 7),
+                   "err_rel_sampled_rows": [float(f"{e:.3e}") for e in errs],
+                   "err_rel_worst_sampled_row": [float(f"{e:.3e}") for e in worst], "fit_after": round(fit, 7),
                    "sweep_passes_over_X": 2 if Context.sweep_uses_dimtree(w.dims, R, prec) else 3},
     }
     print(json.dumps(line), flush=True)
