@@ -107,24 +107,25 @@ __global__ __launch_bounds__(256) void ttm_kernel(TtmArgs a) {
 
   // Staging is branch-free: out-of-range values load C[0] and are zeroed.
   // Element e of the chunk is C row kk = e / R (exact in FP32 for e < 2^12),
-  // column e - kk R.
+  // column e - kk R.  The zeroing happens at the store, so nothing between
+  // the loads (issued at a chunk's start) and the store (at its end) waits
+  // for them.
+  auto stage_ok = [&](int c, int q) {
+    const int e = tid + 256 * q;
+    return e < chunk && (int64_t)c * chunk + e < ctot;
+  };
   auto stage_load = [&](float (&s)[SC], int c) {
 #pragma unroll
-    for (int q = 0; q < SC; ++q) {
-      const int e = tid + 256 * q;
-      const int64_t idx = (int64_t)c * chunk + e;
-      const bool ok = e < chunk && idx < ctot;
-      const float v = a.C[ok ? idx : 0];
-      s[q] = ok ? v : 0.f;
-    }
+    for (int q = 0; q < SC; ++q)
+      s[q] = a.C[stage_ok(c, q) ? (int64_t)c * chunk + tid + 256 * q : 0];
   };
-  auto stage_store = [&](const float (&s)[SC], float* b) {
+  auto stage_store = [&](const float (&s)[SC], int c, float* b) {
 #pragma unroll
     for (int q = 0; q < SC; ++q) {
       const int e = tid + 256 * q;
       const int kk = (int)(((float)e + 0.5f) * inv_r);
       // Values past the chunk (zeros) go to the unread pad of row 0.
-      b[e < chunk ? (e - kk * R) * LDK + kk : KW] = s[q];
+      b[e < chunk ? (e - kk * R) * LDK + kk : KW] = stage_ok(c, q) ? s[q] : 0.f;
     }
   };
   auto frag_load = [&](Frag<PREC, NT, NV>& fr, const float* b) {
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(256) void ttm_kernel(TtmArgs a) {
     {
       float s[SC];
       stage_load(s, chunk_of(0));
-      stage_store(s, lds);
+      stage_store(s, chunk_of(0), lds);
     }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -194,6 +195,7 @@ __global__ __launch_bounds__(256) void ttm_kernel(TtmArgs a) {
       float s[SC];
       const int cn = chunk_of(c + 1);
       if constexpr (!LAST) stage_load(s, cn);
+      __builtin_amdgcn_sched_barrier(0);             // the staging loads stay ahead, unconsumed
       Frag<PREC, NT, NV> fr;
       frag_load(fr, lds + (c & 1) * kBuf);
       __builtin_amdgcn_sched_barrier(0);             // all fragment reads before the MFMAs
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(256) void ttm_kernel(TtmArgs a) {
         }
       }
       if constexpr (!LAST) {
-        stage_store(s, lds + ((c + 1) & 1) * kBuf);
+        stage_store(s, cn, lds + ((c + 1) & 1) * kBuf);
         __syncthreads();
       }
     };
