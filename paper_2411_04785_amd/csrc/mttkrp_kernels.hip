@@ -70,6 +70,36 @@ __device__ __forceinline__ bool run_job(const KArgs& a, float* lds) {
   return true;
 }
 
+// Copy a workgroup's epilogue weights into LDS: the rows F(l0..l1-1, :) are
+// contiguous (n floats from w).  Each thread sends kStageBatch loads before it
+// stores any, so the copy costs a few memory round trips instead of one per
+// element.  SCALE (FP8 modes 1, 2) multiplies row il by 2^sexp[il]; the row
+// of element e is floor((e + 1/2) / R), exact in FP32 for e < 2^22 (n is at
+// most MTK_STAGE_FLOATS).
+constexpr int kStageBatch = 8;
+template <bool SCALE>
+__device__ __forceinline__ void stage_weights(float* wl, const float* w, int n, int R, const int32_t* sexp) {
+  const float inv_r = 1.f / (float)R;
+  for (int base = threadIdx.x; base < n; base += 256 * kStageBatch) {
+    float v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) v[u] = w[min(base + 256 * u, n - 1)];
+    if constexpr (SCALE) {
+      int ex[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int e = min(base + 256 * u, n - 1);
+        ex[u] = sexp[(int)(((float)e + 0.5f) * inv_r)];
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) v[u] = ldexpf(v[u], ex[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      if (base + 256 * u < n) wl[base + 256 * u] = v[u];
+  }
+}
+
 // Tiles kept in flight per wave: deeper for small tiles so that every CU has
 // enough bytes outstanding to cover the HBM latency.
 #ifndef MTK_PIPE_FP8
@@ -117,19 +147,19 @@ __device__ __forceinline__ void load_frag(Frag<PREC, NT, NV>& fr, const KArgs& a
       for (int s = 0; s < NV / 32; ++s) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          uint4 u = make_uint4(0, 0, 0, 0), ul = make_uint4(0, 0, 0, 0);
-          if (col_ok) {
-            u = *reinterpret_cast<const uint4*>(ph + s * 32 + h * 16);
-            ul = *reinterpret_cast<const uint4*>(ph + plane + s * 32 + h * 16);
-          }
+          // Past R the lane holds column 0's codes: its MFMA output column is
+          // never stored and its epilogue weight is zero.  With no select,
+          // all fragment loads go out together.
+          const uint4 u = *reinterpret_cast<const uint4*>(ph + s * 32 + h * 16);
+          const uint4 ul = *reinterpret_cast<const uint4*>(ph + plane + s * 32 + h * 16);
           fr.q[t][s][4 * h + 0] = (int)u.x; fr.q[t][s][4 * h + 1] = (int)u.y;
           fr.q[t][s][4 * h + 2] = (int)u.z; fr.q[t][s][4 * h + 3] = (int)u.w;
           fr.ql[t][s][4 * h + 0] = (int)ul.x; fr.ql[t][s][4 * h + 1] = (int)ul.y;
           fr.ql[t][s][4 * h + 2] = (int)ul.z; fr.ql[t][s][4 * h + 3] = (int)ul.w;
         }
       }
-      fr.sh[t] = col_ok ? 127 + a.frag_exp[col] : 127;          // zero codes past R
-      fr.sl[t] = col_ok ? 127 + a.frag_exp[a.R + col] : 127;
+      fr.sh[t] = 127 + a.frag_exp[col_ok ? col : 0];
+      fr.sl[t] = 127 + a.frag_exp[a.R + (col_ok ? col : 0)];
     }
   }
 }
@@ -182,13 +212,11 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   // slice scale 2^e_i of the loop index), read back with LDS loads so that
   // the only outstanding global loads in the loop are the X prefetches.
   float* wl = dyn_lds;
-  for (int e = threadIdx.x; e < (l1 - l0) * a.R; e += 256) {
-    const int il = e / a.R;
-    float w = a.weight[(int64_t)(l0 + il) * a.R + (e - il * a.R)];
-    if constexpr (PREC == MTK_FP8_E4M3) {
-      if (a.mode != 0) w = ldexpf(w, a.slice_exp[l0 + il]);
-    }
-    wl[e] = w;
+  {
+    const float* w = a.weight + (int64_t)l0 * a.R;
+    const int nw = (l1 - l0) * a.R;
+    if (PREC == MTK_FP8_E4M3 && a.mode != 0) stage_weights<true>(wl, w, nw, a.R, a.slice_exp + l0);
+    else stage_weights<false>(wl, w, nw, a.R, nullptr);
   }
   __syncthreads();
 
@@ -394,7 +422,7 @@ __global__ __launch_bounds__(256) void contract_cm_kernel(KArgs a) {
   const int64_t off0 = (int64_t)(row_ok ? row4 : 0) + (int64_t)red0 * a.sRed;
 
   float* wl = dyn_lds;
-  for (int e = threadIdx.x; e < (l1 - l0) * a.R; e += 256) wl[e] = a.weight[(int64_t)l0 * a.R + e];
+  stage_weights<false>(wl, a.weight + (int64_t)l0 * a.R, (l1 - l0) * a.R, a.R, nullptr);
   __syncthreads();
 
   auto step = [&](const XRegsCM<NV>& x, int it) {
