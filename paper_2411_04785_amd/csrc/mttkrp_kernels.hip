@@ -150,8 +150,9 @@ __device__ __forceinline__ void load_frag(Frag<PREC, NT, NV>& fr, const KArgs& a
           // Past R the lane holds column 0's codes: its MFMA output column is
           // never stored and its epilogue weight is zero.  With no select,
           // all fragment loads go out together.
-          const uint4 u = *reinterpret_cast<const uint4*>(ph + s * 32 + h * 16);
-          const uint4 ul = *reinterpret_cast<const uint4*>(ph + plane + s * 32 + h * 16);
+          const int o = fp8_piece_off(s * 32 + h * 16);
+          const uint4 u = *reinterpret_cast<const uint4*>(ph + o);
+          const uint4 ul = *reinterpret_cast<const uint4*>(ph + plane + o);
           fr.q[t][s][4 * h + 0] = (int)u.x; fr.q[t][s][4 * h + 1] = (int)u.y;
           fr.q[t][s][4 * h + 2] = (int)u.z; fr.q[t][s][4 * h + 3] = (int)u.w;
           fr.ql[t][s][4 * h + 0] = (int)ul.x; fr.ql[t][s][4 * h + 1] = (int)ul.y;
@@ -190,7 +191,8 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   const int cb = cg * NT * 16;                        // first column of this wave
   const int win = rg * a.wr + wred;                   // reduction window of this wave
   const int red_base = win * KW;
-  const int red0 = red_base + g * NV;                 // this lane's first reduction value
+  // This lane's first reduction value (FP8: its first 16-byte piece).
+  const int red0 = red_base + g * (PREC == MTK_FP8_E4M3 ? 16 : NV);
   const int mt = mg * a.mt_per_wg + wm;               // M-tile of this wave
   const int m0 = mt * 16;
   const int row = m0 + m_l;

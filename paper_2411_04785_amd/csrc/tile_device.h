@@ -34,6 +34,14 @@ template <int NV> struct XRegs<MTK_FP8_E4M3, NV> { uint32_t w[NV / 4]; };
 
 // Load this lane's nv reduction values of tile row `m` (global offset `off`
 // of its first value).  `full` means the whole window and row are in range.
+// FP8 lanes hold their nv values as 16-byte pieces: lane group g's element e
+// is at offset 64 (e / 16) + 16 g + e % 16 of the window, so one 16-byte load
+// instruction of a wave reads 64 contiguous bytes of each row.  `red0` and
+// `off` of an FP8 lane point at window offset 16 g; fp8_piece_off(e) is the
+// rest.  The factor fragment uses the same offsets, so A and B elements of a
+// lane pair up on the same reduction index.
+__device__ __forceinline__ constexpr int fp8_piece_off(int e) { return (e >> 4) * 64 + (e & 15); }
+
 template <int PREC, int NV, bool CONTIG, bool VEC, bool full>
 __device__ __forceinline__ void load_x(XRegs<PREC, NV>& x, const void* X, int64_t off,
                                        int64_t sRed, bool row_ok, int red0, int nRed) {
@@ -42,15 +50,15 @@ __device__ __forceinline__ void load_x(XRegs<PREC, NV>& x, const void* X, int64_
     if constexpr (CONTIG && VEC && full) {
 #pragma unroll
       for (int q = 0; q < NV / 16; ++q) {
-        const uint4 u = *reinterpret_cast<const uint4*>(p + q * 16);
+        const uint4 u = *reinterpret_cast<const uint4*>(p + q * 64);
         x.w[4 * q + 0] = u.x; x.w[4 * q + 1] = u.y; x.w[4 * q + 2] = u.z; x.w[4 * q + 3] = u.w;
       }
     } else if constexpr (CONTIG && VEC) {
-      // nRed is a multiple of 16 here, so each 16-byte chunk is all in or all out.
+      // nRed is a multiple of 16 here, so each 16-byte piece is all in or all out.
 #pragma unroll
       for (int q = 0; q < NV / 16; ++q) {
         uint4 u = make_uint4(0, 0, 0, 0);
-        if (row_ok && red0 + 16 * q < nRed) u = *reinterpret_cast<const uint4*>(p + q * 16);
+        if (row_ok && red0 + 64 * q < nRed) u = *reinterpret_cast<const uint4*>(p + q * 64);
         x.w[4 * q + 0] = u.x; x.w[4 * q + 1] = u.y; x.w[4 * q + 2] = u.z; x.w[4 * q + 3] = u.w;
       }
     } else {
@@ -61,9 +69,9 @@ __device__ __forceinline__ void load_x(XRegs<PREC, NV>& x, const void* X, int64_
         uint32_t w = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int e = 4 * q + b;
-          const bool ok = full || (row_ok && red0 + e < nRed);
-          const uint32_t v = *(ok ? p + (int64_t)e * sRed : static_cast<const uint8_t*>(X));
+          const int k = fp8_piece_off(4 * q + b);
+          const bool ok = full || (row_ok && red0 + k < nRed);
+          const uint32_t v = *(ok ? p + (int64_t)k * sRed : static_cast<const uint8_t*>(X));
           w |= (ok ? v : 0u) << (8 * b);
         }
         x.w[q] = w;
