@@ -47,23 +47,35 @@ __host__ __device__ inline size_t gram_part_elems(int R) { return (size_t)gram_p
 
 
 // Accumulate the Gram tile (rows tr*16.., cols ts*16..) over rows [i0, i1) of
-// a factor whose FP32 values val(i, col) are staged 64 rows at a time.
+// a factor staged 64 rows at a time: load(i, col) reads the stored value
+// (as double) and conv(raw, col) turns it into the FP32 factor value.
 // Thread (r, s) = (tid >> 4, tid & 15) sums in increasing row order; both
-// Gram kernels use this one routine, so they agree bit for bit.
-template <class Val, class Emit>
-__device__ double gram_tile_rows(int64_t i0, int64_t i1, int R, int tr, int ts, Val val, Emit emit) {
+// Gram kernels use this one routine, so they agree bit for bit.  A chunk's
+// loads use clamped in-range indices and all go out before any is used.
+template <class Load, class Conv, class Emit>
+__device__ double gram_tile_rows(int64_t i0, int64_t i1, int R, int tr, int ts, Load load, Conv conv, Emit emit) {
   __shared__ float rows_r[64][17];
   __shared__ float rows_s[64][17];
   double acc = 0.0;
   const int tid = threadIdx.x;
+  const int cc = tid & 15;
+  const int cr = tr * 16 + cc, cs = ts * 16 + cc;
+  const int crl = min(cr, R - 1), csl = min(cs, R - 1);
   for (int64_t c0 = i0; c0 < i1; c0 += 64) {
-    for (int e = tid; e < 64 * 16; e += 256) {
-      const int ii = e >> 4, cc = e & 15;
+    double rr[4], rs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = min(c0 + (tid >> 4) + 16 * u, i1 - 1);
+      rr[u] = load(i, crl);
+      rs[u] = tr == ts ? 0.0 : load(i, csl);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ii = (tid >> 4) + 16 * u;
       const int64_t i = c0 + ii;
-      const int cr = tr * 16 + cc, cs = ts * 16 + cc;
       float vr = 0.f, vs = 0.f;
-      if (i < i1 && cr < R) { vr = val(i, cr); emit(i, cr, vr); }
-      if (i < i1 && cs < R) vs = tr == ts ? vr : val(i, cs);
+      if (i < i1 && cr < R) { vr = conv(rr[u], cr); emit(i, cr, vr); }
+      if (i < i1 && cs < R) vs = tr == ts ? vr : conv(rs[u], cs);
       rows_r[ii][cc] = vr;
       rows_s[ii][cc] = vs;
     }
@@ -96,7 +108,8 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ F0,
   const int64_t rows = gram_rows(n, R);
   const int64_t i0 = (int64_t)rb * rows, i1 = min(n, i0 + rows);
   const double acc = gram_tile_rows(
-      i0, i1, R, tr, ts, [&](int64_t i, int c) { return F[i * R + c]; }, [](int64_t, int, float) {});
+      i0, i1, R, tr, ts, [&](int64_t i, int c) { return (double)F[i * R + c]; },
+      [](double v, int) { return (float)v; }, [](int64_t, int, float) {});
   gram_store(acc, f ? P1 : P0, blockIdx.x, rb);
 }
 
@@ -122,14 +135,39 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
   const int tid = threadIdx.x, c = tid & 15, g = tid >> 4;
   const int cb = blockIdx.y * 16;
   const int64_t q0 = (int64_t)blockIdx.x * kApplyRows;
-  for (int e = tid; e < R * 16; e += 256) {
-    const int k = e >> 4, cc = e & 15;
-    Vs[e] = cb + cc < R ? Vinv[(int64_t)k * R + cb + cc] : 0.0;
+  // Staging loads use clamped in-range indices and go out in batches before
+  // any is stored.
+  {
+    constexpr int U = kMaxRank * 16 / 256;
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + 256 * u;
+      const int k = min(e >> 4, R - 1), cc = e & 15;
+      v[u] = Vinv[(int64_t)k * R + min(cb + cc, R - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = tid + 256 * u;
+      if (e < R * 16) Vs[e] = cb + (e & 15) < R ? v[u] : 0.0;
+    }
   }
   const int64_t nrow = min<int64_t>(kApplyRows, n - q0);
-  for (int e = tid; e < kApplyRows * R; e += 256) {
-    const int rr = e / R, k = e - rr * R;
-    Ms[rr][k] = rr < nrow ? M[q0 * R + e] : 0.f;
+  {
+    const int nm = (int)nrow * R;
+    for (int e0 = tid; e0 < kApplyRows * R; e0 += 256 * 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = M[q0 * R + min(e0 + 256 * u, nm - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < kApplyRows * R) {
+          const int rr = e / R, k = e - rr * R;
+          Ms[rr][k] = e < nm ? v[u] : 0.f;
+        }
+      }
+    }
   }
   __syncthreads();
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -191,8 +229,16 @@ __global__ __launch_bounds__(256) void normalize_gram_kernel(const double* __res
   if (ipsum && blockIdx.x == 0 && blockIdx.y == 0) {
     // <F, M> over the whole factor: strided per-thread sums, then a tree, in
     // fixed order.
+    const int64_t ne = (int64_t)nblk * R;
     double t = 0.0;
-    for (int64_t e = tid; e < (int64_t)nblk * R; e += 256) t += ipsum[e];
+    for (int64_t e0 = tid; e0 < ne; e0 += 256 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = ipsum[min(e0 + 256 * u, ne - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e0 + 256 * u < ne) t += v[u];
+    }
     ired[tid] = t;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -207,9 +253,16 @@ __global__ __launch_bounds__(256) void normalize_gram_kernel(const double* __res
     // row blocks b = q, q + 8, ... in order.
     const int u = tid & 31, q = tid >> 5;
     const int col = (u < 16 ? tr : ts) * 16 + (u & 15);
+    const int cl = min(col, R - 1);
     double t = 0.0;
-    if (col < R)
-      for (int b = q; b < nblk; b += 8) t += colsq[(int64_t)b * R + col];
+    for (int b0 = q; b0 < nblk; b0 += 64) {
+      double v[8];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) v[w] = colsq[(int64_t)min(b0 + 8 * w, nblk - 1) * R + cl];
+#pragma unroll
+      for (int w = 0; w < 8; ++w)
+        if (col < R && b0 + 8 * w < nblk) t += v[w];
+    }
     lsum[q][u] = t;
   }
   __syncthreads();
@@ -225,15 +278,15 @@ __global__ __launch_bounds__(256) void normalize_gram_kernel(const double* __res
   const int rb = blockIdx.y;
   const int64_t rows = gram_rows(n, R);
   const int64_t i0 = (int64_t)rb * rows, i1 = min(n, i0 + rows);
-  auto val = [&](int64_t i, int col) {
+  auto load = [&](int64_t i, int col) { return F[i * R + col]; };
+  auto conv = [&](double f, int col) {
     const double l = lt[col / 16 == tr ? (col & 15) : 16 + (col & 15)];
-    const double f = F[i * R + col];
     return (float)(l > 0.0 ? f / l : f);
   };
   auto emit = [&](int64_t i, int col, float v) {
     if (diag) out[i * R + col] = v;
   };
-  const double acc = gram_tile_rows(i0, i1, R, tr, ts, val, emit);
+  const double acc = gram_tile_rows(i0, i1, R, tr, ts, load, conv, emit);
   gram_store(acc, part, blockIdx.x, rb);
 }
 
