@@ -517,10 +517,18 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restr
   const int eo = threadIdx.x & 31;
   const int q = threadIdx.x >> 5;
   const int64_t e = (int64_t)blockIdx.x * 32 + eo;
+  // Slices q, q + 8, ... in order; their loads go out 8 at a time (clamped
+  // to the last slice) ahead of the adds.
   float s = 0.f;
   if (e < n) {
-#pragma unroll 4
-    for (int k = q; k < S; k += 8) s += part[(int64_t)k * n + e];
+    for (int k0 = q; k0 < S; k0 += 64) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)min(k0 + 8 * u, S - 1) * n + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + 8 * u < S) s += v[u];
+    }
   }
   red[q][eo] = s;
   __syncthreads();
@@ -557,29 +565,50 @@ __global__ __launch_bounds__(256) void frag_quant_kernel(const float* __restrict
   const int64_t plane = (int64_t)R * red_pad;
   uint8_t* qh = q + (int64_t)r * red_pad;
   uint8_t* ql = qh + plane;
+  // Each pass reads the column 4 values per thread at a time (clamped to the
+  // last row, loads ahead of their use); values at i >= nRed are unused.
+  constexpr int U = 4;
+  auto col4 = [&](int i0, float (&g)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) g[u] = G[(int64_t)min(i0 + 256 * u, nRed - 1) * R + r];
+  };
   float m = 0.f;
-  for (int i = threadIdx.x; i < nRed; i += 256) m = fmaxf(m, fabsf(G[(int64_t)i * R + r]));
+  for (int i0 = threadIdx.x; i0 < nRed; i0 += 256 * U) {
+    float g[U];
+    col4(i0, g);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + 256 * u < nRed) m = fmaxf(m, fabsf(g[u]));
+  }
   const int eh = scale_exponent_dev(block_max(m, smax));
   const float ih = ldexpf(1.f, -eh), sh = ldexpf(1.f, eh);
   float mr = 0.f;
-  for (int i = threadIdx.x; i < red_pad; i += 256) {
-    uint32_t c = 0;
-    if (i < nRed) {
-      const float g = G[(int64_t)i * R + r];
-      c = e4m3_encode_dev(g * ih);
-      mr = fmaxf(mr, fabsf(g - e4m3_decode_dev(c) * sh));
+  for (int i0 = threadIdx.x; i0 < red_pad; i0 += 256 * U) {
+    float g[U];
+    col4(i0, g);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 256 * u;
+      uint32_t c = 0;
+      if (i < nRed) {
+        c = e4m3_encode_dev(g[u] * ih);
+        mr = fmaxf(mr, fabsf(g[u] - e4m3_decode_dev(c) * sh));
+      }
+      if (i < red_pad) qh[i] = static_cast<uint8_t>(c);
     }
-    qh[i] = static_cast<uint8_t>(c);
   }
   const int el = scale_exponent_dev(block_max(mr, smax));
   const float il = ldexpf(1.f, -el);
-  for (int i = threadIdx.x; i < red_pad; i += 256) {
-    uint32_t c = 0;
-    if (i < nRed) {
-      const float g = G[(int64_t)i * R + r];
-      c = e4m3_encode_dev((g - e4m3_decode_dev(qh[i]) * sh) * il);
+  for (int i0 = threadIdx.x; i0 < red_pad; i0 += 256 * U) {
+    float g[U];
+    col4(i0, g);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 256 * u;
+      uint32_t c = 0;
+      if (i < nRed) c = e4m3_encode_dev((g[u] - e4m3_decode_dev(qh[i]) * sh) * il);
+      if (i < red_pad) ql[i] = static_cast<uint8_t>(c);
     }
-    ql[i] = static_cast<uint8_t>(c);
   }
   if (threadIdx.x == 0) {
     ex[r] = eh;
