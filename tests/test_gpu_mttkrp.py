@@ -141,7 +141,13 @@ def test_fp8_quantize_bit_exact(ctx):
     assert np.array_equal(host(q), qo)
 
 
-@pytest.mark.parametrize("dims,R", [((40, 33, 50), 16), ((64, 64, 160), 128), ((31, 70, 130), 40)])
+# Lanes hold 32, 64 or 128 values as 16-byte pieces; the last four cases have
+# long reductions (608: 16-byte loads, 600: byte loads; 528 in mode 3, also
+# strided) so that 64- and 128-value lanes (R <= 32) and a ragged last window
+# are exercised.
+@pytest.mark.parametrize("dims,R", [((40, 33, 50), 16), ((64, 64, 160), 128), ((31, 70, 130), 40),
+                                    ((20, 24, 608), 16), ((20, 24, 608), 32), ((18, 22, 600), 32),
+                                    ((12, 528, 20), 16)])
 def test_fp8_mttkrp(ctx, dims, R):
     from gpu_util import dev, host, rel
     X, facs = _sliced_case(dims, R, seed=11)
@@ -155,14 +161,27 @@ def test_fp8_mttkrp(ctx, dims, R):
         _say("fp8", dims, R, mode)
         got = host(ctx.mttkrp(q, fd, mode, "fp8", slice_exp=e, X_t=qt))
         if mode == 2:
-            # The strided path (no transposed copy) must give the same bits.
+            # The strided path (no transposed copy) gives the same bits while
+            # the reduction over j is one window (32 values per lane, J <=
+            # 128); with more windows the two plans add the windows in a
+            # different order (in-workgroup vs split-K), so the results agree
+            # to FP32 rounding and each meets the oracle bar below.
             plain = host(ctx.mttkrp(q, fd, mode, "fp8", slice_exp=e))
-            assert np.array_equal(plain, got)
+            _say("fp8 strided vs transposed", rel(plain, got))
+            if dims[1] <= 128:
+                assert np.array_equal(plain, got)
+            else:
+                assert rel(plain, got) <= 1e-6
+                assert rel(plain, oracle.mttkrp(Xq, facs, mode)) <= 5e-3
         ref = oracle.mttkrp(X, facs, mode)
-        assert rel(got, ref) <= 3e-2
+        # 3e-2 against the unquantised tensor; on a small tensor the tensor's
+        # own e4m3 rounding (the oracle on the dequantised tensor) can pass
+        # that alone, and then the bar is that error plus the factor term.
+        refq = oracle.mttkrp(Xq, facs, mode)
+        assert rel(got, ref) <= max(3e-2, rel(refq, ref) + 5e-3)
         # Against the dequantised tensor only the factor's two-term e4m3
         # rounding (about 2^-8 relative per entry) remains.
-        assert rel(got, oracle.mttkrp(Xq, facs, mode)) <= 5e-3
+        assert rel(got, refq) <= 5e-3
         # Worst output row: per-slice scaling keeps the 1e-3 slices as accurate
         # as the 1e3 ones (an underflowed slice would show an error near 1).
         if mode == 0:
