@@ -41,7 +41,7 @@ __host__ __device__ inline int gram_blocks(int64_t n, int R) {
 }
 __host__ __device__ inline int64_t gram_rows(int64_t n, int R) { return cdiv(n, gram_blocks(n, R)); }
 // Rows per workgroup of the apply kernel.
-constexpr int kApplyRows = 64;
+constexpr int kApplyRows = 16;
 // Size of one factor's Gram partials: [tile pair][row block][16 x 16].
 __host__ __device__ inline size_t gram_part_elems(int R) { return (size_t)gram_pairs(R) * kGramBlocksMax * 256; }
 
@@ -121,13 +121,16 @@ __global__ __launch_bounds__(256) void gj_inv_kernel(FactorArgs f) {
   factor_gj<B>(f, lds);
 }
 
-// F = M V^{-1}: workgroup (row block of 64, column block of 16); thread
-// (g, c) owns column c of rows g, g + 16, g + 32, g + 48.  Also writes the
-// row block's sums of F^2 per column (rows in a fixed order).
-__global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M, int64_t n, int R,
-                                                    const double* __restrict__ Vinv, const int* __restrict__ status,
-                                                    double* __restrict__ F, double* __restrict__ colsq,
-                                                    double* __restrict__ ipsum) {
+// F = M V^{-1}: workgroup (row block of 16, column block of 16); thread
+// (g, c) owns row g, column c.  M arrives as S split-K slices, sstride floats
+// apart, added here in the split-K reduction's order (slice k into partial
+// k mod 8 in increasing k, then the 8 partials in order), so an update can
+// take them without a separate reduction; S = 1 is a plain M.  Also writes
+// the row block's sums of F^2 per column (rows in a fixed order).
+__global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M, int S, int64_t sstride, int64_t n,
+                                                    int R, const double* __restrict__ Vinv,
+                                                    const int* __restrict__ status, double* __restrict__ F,
+                                                    double* __restrict__ colsq, double* __restrict__ ipsum) {
   if (*status & kStatusNotSPD) return;
   __shared__ double Vs[kMaxRank * 16];
   __shared__ float Ms[kApplyRows][kMaxRank + 1];
@@ -153,12 +156,13 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
     }
   }
   const int64_t nrow = min<int64_t>(kApplyRows, n - q0);
-  {
-    const int nm = (int)nrow * R;
+  const int nm = (int)nrow * R;
+  const float* Mb = M + q0 * R;
+  if (S == 1) {
     for (int e0 = tid; e0 < kApplyRows * R; e0 += 256 * 8) {
       float v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = M[q0 * R + min(e0 + 256 * u, nm - 1)];
+      for (int u = 0; u < 8; ++u) v[u] = Mb[min(e0 + 256 * u, nm - 1)];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + 256 * u;
@@ -168,25 +172,36 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
         }
       }
     }
+  } else {
+    for (int e = tid; e < kApplyRows * R; e += 256) {
+      const float* src = Mb + min(e, nm - 1);
+      float p8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      for (int k0 = 0; k0 < S; k0 += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = src[(int64_t)min(k0 + u, S - 1) * sstride];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (k0 + u < S) p8[u & 7] += v[u];
+      }
+      float t = p8[0];
+#pragma unroll
+      for (int q = 1; q < 8; ++q) t += p8[q];
+      const int rr = e / R, k = e - rr * R;
+      Ms[rr][k] = e < nm ? t : 0.f;
+    }
   }
   __syncthreads();
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc = 0.0;
 #pragma unroll 4
-  for (int k = 0; k < R; ++k) {
-    const double v = Vs[k * 16 + c];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) acc[m] = fma((double)Ms[g + 16 * m][k], v, acc[m]);
-  }
+  for (int k = 0; k < R; ++k) acc = fma((double)Ms[g][k], Vs[k * 16 + c], acc);
   double s = 0.0, ip = 0.0;
   const int col = cb + c;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int64_t q = q0 + g + 16 * m;
-    if (q < n && col < R) {
-      F[q * R + col] = acc[m];
-      s = fma(acc[m], acc[m], s);
-      ip = fma(acc[m], (double)Ms[g + 16 * m][col], ip);
-    }
+  const int64_t q = q0 + g;
+  if (q < n && col < R) {
+    F[q * R + col] = acc;
+    s = acc * acc;
+    ip = acc * (double)Ms[g][col];
   }
   red[g][c] = s;
   __syncthreads();
@@ -382,11 +397,17 @@ hipError_t launch_factor(const int64_t dims[3], int R, int mode, int64_t maxdim,
 
 hipError_t launch_apply(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
                         int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip) {
+  return launch_apply(dims, R, mode, MSlices{M, 1, 0}, factor_out, lambda, maxdim, ws, status, st, with_ip);
+}
+
+hipError_t launch_apply(const int64_t dims[3], int R, int mode, const MSlices& m, float* factor_out, double* lambda,
+                        int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip) {
   const int64_t n = dims[mode];
+  if (m.slices < 1 || (m.slices > 1 && m.sstride < n * R)) return hipErrorInvalidValue;
   SolveWs w = solve_ws(maxdim, R, ws);
   const int nblk = (int)cdiv(n, kApplyRows);
-  hipLaunchKernelGGL(apply_kernel, dim3(nblk, (R + 15) / 16), dim3(256), 0, st, M, n, R, w.Vinv, status, w.F,
-                     w.colsq, with_ip ? w.ipsum : nullptr);
+  hipLaunchKernelGGL(apply_kernel, dim3(nblk, (R + 15) / 16), dim3(256), 0, st, m.p, m.slices, m.sstride, n, R,
+                     w.Vinv, status, w.F, w.colsq, with_ip ? w.ipsum : nullptr);
   hipLaunchKernelGGL(normalize_gram_kernel, dim3(gram_pairs(R), gram_blocks(n, R)), dim3(256), 0, st, w.F, n, R, w.colsq,
                      nblk, status, lambda, factor_out, w.part[mode], with_ip ? w.ipsum : nullptr,
                      with_ip ? w.ip : nullptr);
@@ -395,9 +416,14 @@ hipError_t launch_apply(const int64_t dims[3], int R, int mode, const float* M, 
 
 hipError_t launch_update(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
                          int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip) {
+  return launch_update(dims, R, mode, MSlices{M, 1, 0}, factor_out, lambda, maxdim, ws, status, st, with_ip);
+}
+
+hipError_t launch_update(const int64_t dims[3], int R, int mode, const MSlices& m, float* factor_out,
+                         double* lambda, int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip) {
   hipError_t e = launch_factor(dims, R, mode, maxdim, ws, status, st);
   if (e != hipSuccess) return e;
-  return launch_apply(dims, R, mode, M, factor_out, lambda, maxdim, ws, status, st, with_ip);
+  return launch_apply(dims, R, mode, m, factor_out, lambda, maxdim, ws, status, st, with_ip);
 }
 
 hipError_t launch_gram_solve(const float* const factors[3], const int64_t dims[3], int R, int mode,

@@ -359,14 +359,16 @@ static void* sweep_dimtree_ws(mtk_ctx* c, const int64_t dims[3], int R, int prec
   return static_cast<char*>(sweep_solve_ws(c, dims, R, prec)) + mtk::solve_ws_bytes(maxdim, R);
 }
 
-// The mode-n MTTKRP of a sweep: modes 0 and 1 from the dimension tree when
-// the sweep uses one (dt_ws != nullptr), otherwise the direct contraction.
+// The mode-n MTTKRP of a sweep, into *ms: modes 0 and 1 from the dimension
+// tree when the sweep uses one (dt_ws != nullptr; its split-K slices go to
+// the update unreduced), otherwise the direct contraction into M.
 static mtk_status sweep_mttkrp(mtk_ctx* c, const mtk_tensor* X, const float* const cf[3], int R, int n, int prec,
-                               float* M, void* scratch, void* dt_ws, hipStream_t st,
+                               float* M, void* scratch, void* dt_ws, hipStream_t st, mtk::MSlices* ms,
                                const mtk::FactorArgs* job = nullptr) {
+  *ms = mtk::MSlices{M, 1, 0};
   if (dt_ws && n < 2) {
     hipError_t e = mtk::launch_dimtree_mttkrp(n, n == 0, static_cast<const float*>(X->data), aligned16(X->data),
-                                              X->dims, cf, R, prec, M, dt_ws, st, job);
+                                              X->dims, cf, R, prec, M, dt_ws, st, job, ms);
     if (e != hipSuccess) return hip_fail(c, e, "dimension-tree launch");
     return MTK_OK;
   }
@@ -401,17 +403,19 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
   for (int n = 0; n < 3; ++n) {
     if (R <= mtk::kJobMaxRank) {
       const mtk::FactorArgs f = mtk::factor_args(X->dims, R, n, maxdim, solve_ws, c->d_status);
-      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st, &f);
+      mtk::MSlices ms;
+      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st, &ms, &f);
       if (s != MTK_OK) return s;
-      hipError_t e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st,
+      hipError_t e = mtk::launch_apply(X->dims, R, n, ms, factors[n], lambda, maxdim, solve_ws, c->d_status, st,
                                        n == 2);
       if (e != hipSuccess) return hip_fail(c, e, "update launch");
       continue;
     }
     if (!overlap) {
-      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st);
+      mtk::MSlices ms;
+      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st, &ms);
       if (s != MTK_OK) return s;
-      hipError_t e = mtk::launch_update(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st,
+      hipError_t e = mtk::launch_update(X->dims, R, n, ms, factors[n], lambda, maxdim, solve_ws, c->d_status, st,
                                         n == 2);
       if (e != hipSuccess) return hip_fail(c, e, "update launch");
       continue;
@@ -421,10 +425,11 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
     hipError_t e = mtk::launch_factor(X->dims, R, n, maxdim, solve_ws, c->d_status, c->side);
     if (e != hipSuccess) return hip_fail(c, e, "factorisation launch");
     HIP_OR_FAIL(c, hipEventRecord(c->join_ev[n], c->side));
-    mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st);
+    mtk::MSlices ms;
+    mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st, &ms);
     if (s != MTK_OK) return s;
     HIP_OR_FAIL(c, hipStreamWaitEvent(st, c->join_ev[n], 0));
-    e = mtk::launch_apply(X->dims, R, n, M, factors[n], lambda, maxdim, solve_ws, c->d_status, st, n == 2);
+    e = mtk::launch_apply(X->dims, R, n, ms, factors[n], lambda, maxdim, solve_ws, c->d_status, st, n == 2);
     if (e != hipSuccess) return hip_fail(c, e, "update launch");
   }
   if (with_fit) {

@@ -331,7 +331,7 @@ size_t dimtree_ws_bytes(const int64_t dims[3], int R) {
 
 hipError_t launch_dimtree_mttkrp(int mode, bool form_y, const float* X, bool x_aligned16, const int64_t dims[3],
                                  const float* const factors[3], int R, int prec, float* out, void* ws,
-                                 hipStream_t st, const FactorArgs* job) {
+                                 hipStream_t st, const FactorArgs* job, MSlices* defer) {
   if ((mode != 0 && mode != 1) || (prec != MTK_FP32 && prec != MTK_BF16X3) || R < 1 || R > kMaxRank)
     return hipErrorInvalidValue;
   if (job && job->R > kJobMaxRank) return hipErrorInvalidValue;
@@ -374,6 +374,10 @@ hipError_t launch_dimtree_mttkrp(int mode, bool form_y, const float* X, bool x_a
   const int64_t grid = cdiv64(y.nO, 256 / R) * slices + y.job_on;
   hipLaunchKernelGGL(ysum_kernel, dim3((unsigned)grid), dim3(256), lds, st, y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (defer) {
+    *defer = MSlices{slices > 1 ? part : out, slices, (int64_t)y.nO * R};
+    return hipSuccess;
+  }
   if (slices > 1) return launch_slice_reduce(part, slices, (int64_t)y.nO * R, out, st);
   return hipSuccess;
 }

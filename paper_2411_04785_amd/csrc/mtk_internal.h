@@ -81,13 +81,24 @@ hipError_t launch_slice_reduce(const float* part, int slices, int64_t n, float* 
 // X and C (the mode-1 update of a sweep reuses the mode-0 update's Y).
 // FP32 / BF16X3, FP32 tensor.  `ws`: dimtree_ws_bytes.  `job` (R <=
 // kJobMaxRank) rides in the mode-0 Y launch or the mode-1 sum.
+// An MTTKRP result as handed to an update: `slices` split-K partial slices
+// (`sstride` floats apart) that the update adds in the split-K reduction's
+// order, bit for bit; slices == 1 is the plain n x R matrix.
+struct MSlices {
+  const float* p;
+  int slices;
+  int64_t sstride;
+};
 // Largest dims[0]*dims[1] (rows of Y) the tree takes.
 constexpr int64_t kDimtreeMaxRows = (int64_t)1 << 36;
 bool dimtree_used(const int64_t dims[3], int R, int prec);
 size_t dimtree_ws_bytes(const int64_t dims[3], int R);
+// defer != nullptr: the sum's split-K slices are left in ws and described in
+// *defer for an update to add (no reduction launch); out is then unused
+// unless the sum has a single slice.
 hipError_t launch_dimtree_mttkrp(int mode, bool form_y, const float* X, bool x_aligned16, const int64_t dims[3],
                                  const float* const factors[3], int R, int prec, float* out, void* ws,
-                                 hipStream_t st, const FactorArgs* job);
+                                 hipStream_t st, const FactorArgs* job, MSlices* defer = nullptr);
 
 // FP8 tensor preparation (per mode-1 slice power-of-two scaled e4m3).
 hipError_t launch_quantize_slices(const float* x, int64_t I, int64_t J, int64_t K, uint8_t* q,
@@ -122,6 +133,10 @@ hipError_t launch_factor(const int64_t dims[3], int R, int mode, int64_t maxdim,
                          hipStream_t st);
 hipError_t launch_apply(const int64_t dims[3], int R, int mode, const float* M, float* factor_out, double* lambda,
                         int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip = false);
+hipError_t launch_apply(const int64_t dims[3], int R, int mode, const MSlices& m, float* factor_out, double* lambda,
+                        int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip = false);
+hipError_t launch_update(const int64_t dims[3], int R, int mode, const MSlices& m, float* factor_out,
+                         double* lambda, int64_t maxdim, void* ws, int* status, hipStream_t st, bool with_ip = false);
 // Device address of the <F, M> scalar in a solve region laid out for maxdim.
 const double* solve_ip(int64_t maxdim, int R, void* ws);
 // launch_grams of the two other factors followed by launch_update.

@@ -233,8 +233,9 @@ struct mtk_server {
       for (int n = 0; n < 3; ++n) {
         const mtk::FactorArgs job = mtk::factor_args(r.dims, R, n, maxdim, solve_ws, s.d_status);
         const mtk::FactorArgs* jp = R <= mtk::kJobMaxRank ? &job : nullptr;
+        mtk::MSlices ms{M, 1, 0};
         if (dt_ws && n < 2) {
-          e = mtk::launch_dimtree_mttkrp(n, n == 0, X, true, r.dims, cf, R, r.prec, M, dt_ws, s.st, jp);
+          e = mtk::launch_dimtree_mttkrp(n, n == 0, X, true, r.dims, cf, R, r.prec, M, dt_ws, s.st, jp, &ms);
         } else {
           const float* fr = n == 2 ? f[1] : f[2];
           const float* wt = n == 0 ? f[1] : f[0];
@@ -242,8 +243,8 @@ struct mtk_server {
           e = mtk::launch_contract(p, r.prec, n, X, nullptr, fr, wt, M, scratch, s.st, jp);
         }
         if (e != hipSuccess) return e;
-        e = jp ? mtk::launch_apply(r.dims, R, n, M, f[n], lam, maxdim, solve_ws, s.d_status, s.st)
-               : mtk::launch_update(r.dims, R, n, M, f[n], lam, maxdim, solve_ws, s.d_status, s.st);
+        e = jp ? mtk::launch_apply(r.dims, R, n, ms, f[n], lam, maxdim, solve_ws, s.d_status, s.st)
+               : mtk::launch_update(r.dims, R, n, ms, f[n], lam, maxdim, solve_ws, s.d_status, s.st);
         if (e != hipSuccess) return e;
       }
     }
