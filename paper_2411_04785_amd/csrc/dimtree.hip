@@ -60,6 +60,13 @@ struct TtmArgs {
   int K, R;
   int job_on;         // 1: workgroup 0 inverts job's V, the rest shift by one
   FactorArgs job;
+  // Optional sum M1(i, r) = sum_j Y(i, j, r) B(j, r) while Y is formed, for
+  // J a multiple of a workgroup's rows (each workgroup's rows share one i):
+  // workgroup b writes the partial row m1part[s][i][:] of its J-block s.
+  const float* B;     // J x R, or nullptr
+  float* m1part;      // (J / rows per workgroup) x I x R
+  int J;
+  int64_t I;
 };
 
 __device__ __forceinline__ void run_factor_job(const FactorArgs& f, void* lds) {
@@ -231,6 +238,45 @@ __global__ __launch_bounds__(256) void ttm_kernel(TtmArgs a) {
         if (row < a.P) a.Y[row * R + col] = acc[rt][t][v];
       }
     }
+
+  if (a.B) {
+    // All rows of the workgroup have the same i (the launcher checks J).
+    // Lane sums over its rows (rt, then v), then lane groups g and waves
+    // in order through LDS: one fixed summation order.
+    const int64_t pw = blk * (int64_t)(64 * RT);
+    const int64_t i = pw / a.J;
+    const int jb = (int)(pw - i * a.J);
+    const int sl = jb / (64 * RT);
+    float bv[RT][4][NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int j = (int)(p0 - i * a.J) + rt * 16 + g * 4 + v;
+          bv[rt][v][t] = a.B[(int64_t)j * R + min(t * 16 + n, R - 1)];
+        }
+    float sv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      sv[t] = 0.f;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sv[t] = fmaf(acc[rt][t][v], bv[rt][v][t], sv[t]);
+    }
+    __syncthreads();                                  // LDS chunk buffers are free from here
+    float* red = lds;                                 // [wave][g][NT * 16]
+#pragma unroll
+    for (int t = 0; t < NT; ++t) red[(wave * 4 + g) * (NT * 16) + t * 16 + n] = sv[t];
+    __syncthreads();
+    if (tid < R) {
+      float m = 0.f;
+      for (int q = 0; q < 16; ++q) m += red[q * (NT * 16) + tid];
+      a.m1part[((int64_t)sl * a.I + i) * R + tid] = m;
+    }
+  }
 }
 
 struct YsumArgs {
@@ -313,6 +359,19 @@ void ysum_split(int nO, int nQ, int R, int& slices, int& qper) {
 
 size_t r256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Rows of Y per workgroup of the Y kernel (64 per row tile).
+int ttm_rows_per_wg(int R) {
+  const int nt = (R + 15) / 16;
+  return 64 * (nt <= 2 ? MTK_TTM_RT_A : (nt <= 4 ? MTK_TTM_RT_B : 2));
+}
+
+// Partial slices of M1 summed inside the Y kernel, or 0 where J is not a
+// multiple of its rows per workgroup (then the Y-sum kernel runs).
+int64_t ttm_fused_slices(const int64_t dims[3], int R) {
+  const int rw = ttm_rows_per_wg(R);
+  return dims[1] % rw == 0 ? dims[1] / rw : 0;
+}
+
 }  // namespace
 
 bool dimtree_used(const int64_t dims[3], int R, int prec) {
@@ -325,7 +384,8 @@ size_t dimtree_ws_bytes(const int64_t dims[3], int R) {
   int s0, q0, s1, q1;
   ysum_split((int)dims[0], (int)dims[1], R, s0, q0);
   ysum_split((int)dims[1], (int)dims[0], R, s1, q1);
-  const size_t part = std::max((size_t)s0 * dims[0], (size_t)s1 * dims[1]) * R * sizeof(float);
+  const size_t fs = (size_t)ttm_fused_slices(dims, R);
+  const size_t part = std::max({(size_t)s0 * dims[0], (size_t)s1 * dims[1], fs * dims[0]}) * R * sizeof(float);
   return r256((size_t)dims[0] * dims[1] * R * sizeof(float)) + r256(part);
 }
 
@@ -340,6 +400,8 @@ hipError_t launch_dimtree_mttkrp(int mode, bool form_y, const float* X, bool x_a
   float* Y = static_cast<float*>(ws);
   float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + r256((size_t)I * J * R * sizeof(float)));
   hipError_t e;
+  // Mode 0 with Y formed here: M1 comes out of the Y kernel when J allows.
+  const int64_t fused = (mode == 0 && form_y) ? ttm_fused_slices(dims, R) : 0;
   if (form_y) {
     TtmArgs t{};
     t.X = X;
@@ -350,9 +412,23 @@ hipError_t launch_dimtree_mttkrp(int mode, bool form_y, const float* X, bool x_a
     t.R = R;
     t.job_on = (job && mode == 0) ? 1 : 0;
     if (t.job_on) t.job = *job;
+    if (fused) {
+      t.B = factors[1];
+      t.m1part = fused > 1 ? part : out;
+      t.J = (int)J;
+      t.I = I;
+    }
     const bool vec = x_aligned16 && K % 4 == 0;
     e = prec == MTK_FP32 ? launch_ttm_prec<MTK_FP32>(t, vec, st) : launch_ttm_prec<MTK_BF16X3>(t, vec, st);
     if (e != hipSuccess) return e;
+    if (fused) {
+      if (defer) {
+        *defer = MSlices{fused > 1 ? part : out, (int)fused, I * R};
+        return hipSuccess;
+      }
+      if (fused > 1) return launch_slice_reduce(part, (int)fused, I * R, out, st);
+      return hipSuccess;
+    }
   }
   YsumArgs y{};
   y.Y = Y;
