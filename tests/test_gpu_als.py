@@ -125,7 +125,7 @@ def test_als_resume_bitwise(ctx):
         assert np.array_equal(host(x), host(y))
 
 
-@pytest.mark.parametrize("dims,R", [((40, 36, 24), 4), ((40, 36, 32), 4), ((50, 45, 400), 40)])
+@pytest.mark.parametrize("dims,R", [((40, 36, 24), 4), ((40, 36, 32), 4), ((50, 45, 400), 40), ((6, 512, 40), 4)])
 def test_graph_replay_equals_eager(ctx, dims, R):
     # One captured sweep == the same calls made one by one, bitwise: modes 0
     # and 1 by mttkrp_dimtree where the sweep uses the dimension tree.
@@ -155,10 +155,12 @@ def test_graph_replay_equals_eager(ctx, dims, R):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("dims,R", [((70, 45, 200), 20), ((33, 40, 330), 40)])
+@pytest.mark.parametrize("dims,R", [((70, 45, 200), 20), ((33, 40, 330), 40), ((12, 256, 160), 16),
+                                    ((10, 512, 400), 40)])
 def test_dimtree_sweeps_match_oracle(ctx, prec, dims, R):
     # Sweeps whose first two updates come from Y = X x3 C (ragged row tiles
-    # and C chunks; R = 20 carries the inversion inside the Y launches).
+    # and C chunks; R <= 32 carries the inversion inside the Y launches; J =
+    # 256 and 512: mode 0's sum formed inside the Y kernel, in 1 and 2 slices).
     from gpu_util import dev, host, rel
     from paper_2411_04785_amd.mttkrp import Context
     assert Context.sweep_uses_dimtree(dims, R, prec)

@@ -222,6 +222,12 @@ DIMTREE = [
     ((70, 30, 131), 32),
     ((9, 11, 66), 8),
     ((16, 16, 64), 80),
+    # J a multiple of the Y kernel's rows per workgroup (256; 128 above R =
+    # 64): mode 0's sum is formed inside the Y kernel, in J/256 (J/128) slices.
+    ((6, 256, 48), 8),
+    ((4, 512, 40), 40),
+    ((3, 256, 30), 72),
+    ((2, 768, 20), 128),
 ]
 
 
