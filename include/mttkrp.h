@@ -87,7 +87,9 @@ typedef struct {
 } mtk_tensor;
 
 /* Create a context on HIP device `device` (makes it current).  The context
- * owns a workspace that grows on demand and a sticky device status word. */
+ * owns a workspace that grows on demand and a sticky device status word.
+ * Growing the workspace allocates a larger block without waiting for the
+ * device; the outgrown block is kept until mtk_graph_reset or mtk_destroy. */
 mtk_status mtk_create(mtk_ctx** ctx, int device);
 
 /* Destroy a context, its workspace and its graph cache.  NULL is a no-op. */
@@ -216,7 +218,10 @@ mtk_status als_run(mtk_ctx* ctx, const mtk_tensor* X, float* const factors[3], d
                    int64_t R, int prec, int max_sweeps, double tol, double* fits_host,
                    int* sweeps_done, double* fit_final, void* stream);
 
-/* Drop every cached als_sweep graph of this context. */
+/* Drop every cached als_sweep graph of this context and free the workspace
+ * blocks it outgrew (a growing workspace keeps its old block, and the
+ * graphs that use it, alive rather than wait for the device; they are
+ * released here and by mtk_destroy).  Synchronises the device. */
 mtk_status mtk_graph_reset(mtk_ctx* ctx);
 
 /* ---------------------------------------------------------------------

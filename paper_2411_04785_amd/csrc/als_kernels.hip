@@ -471,12 +471,16 @@ __global__ __launch_bounds__(256) void fit_partial_kernel(const void* __restrict
                                                           int64_t I, int64_t J, int64_t K,
                                                           const float* __restrict__ A, const float* __restrict__ B,
                                                           const float* __restrict__ C,
-                                                          const double* __restrict__ lam, int R,
+                                                          const double* __restrict__ lam, int R, int64_t nbx,
                                                           double* __restrict__ part) {
-  const int64_t i = blockIdx.y;
+  __shared__ double sr[256], sn[256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, g = lane >> 4;
-  const int64_t jw = ((int64_t)blockIdx.x * 4 + wave) * (16 * JT);   // first j of this wave
+  // Work item b = (slice i, j block bx), i = b / nbx; the grid strides over
+  // the I * nbx items, so no grid dimension grows with I.
+  for (int64_t b = blockIdx.x; b < I * nbx; b += gridDim.x) {
+  const int64_t i = b / nbx;
+  const int64_t jw = ((b - i * nbx) * 4 + wave) * (16 * JT);   // first j of this wave
   double w[JT][RQ];
 #pragma unroll
   for (int t = 0; t < JT; ++t)
@@ -540,7 +544,6 @@ __global__ __launch_bounds__(256) void fit_partial_kernel(const void* __restrict
       }
     }
   }
-  __shared__ double sr[256], sn[256];
   sr[threadIdx.x] = res;
   sn[threadIdx.x] = nrm;
   __syncthreads();
@@ -549,9 +552,10 @@ __global__ __launch_bounds__(256) void fit_partial_kernel(const void* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const int64_t b = i * gridDim.x + blockIdx.x;
     part[2 * b] = sr[0];
     part[2 * b + 1] = sn[0];
+  }
+  __syncthreads();                    // sr / sn are reused by the next item
   }
 }
 
@@ -586,10 +590,13 @@ hipError_t launch_fit(const void* X, int fmt, const int32_t* slice_exp, const in
   const int rq = R <= 8 ? 2 : R <= 16 ? 4 : R <= 32 ? 8 : R <= 64 ? 16 : 32;
   const int jt = rq <= 16 ? 2 : 1;
   const int64_t nbx = cdiv(dims[1], 64 * jt);
-  const dim3 grid((unsigned)nbx, (unsigned)dims[0]);
+  // One workgroup per (slice, j block) up to a grid of 2^20; beyond that the
+  // workgroups stride over the items (same partials, same order).
+  const int64_t items = dims[0] * nbx;
+  const dim3 grid((unsigned)std::min<int64_t>(items, (int64_t)1 << 20));
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, X, fmt, slice_exp, dims[0], dims[1], dims[2], factors[0],
-                       factors[1], factors[2], lambda, R, part);
+                       factors[1], factors[2], lambda, R, nbx, part);
   };
   switch (rq) {
     case 2: go(fit_partial_kernel<2, 2>); break;

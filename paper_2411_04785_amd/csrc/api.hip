@@ -33,6 +33,7 @@ struct GraphKey {
 struct GraphCache {
   hipStream_t capture_stream = nullptr;
   std::map<GraphKey, hipGraphExec_t> execs;
+  std::vector<hipGraphExec_t> retired;   // no longer looked up; may still be in flight
   std::vector<hipGraph_t> graphs;
 };
 
@@ -51,6 +52,15 @@ mtk_status hip_fail(mtk_ctx* c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
   } while (0)
 
+// Move every cached sweep graph out of the lookup (they reference the old
+// workspace); they are destroyed by mtk_graph_reset / mtk_destroy.
+void retire_graphs(mtk_ctx* c) {
+  GraphCache* gc = static_cast<GraphCache*>(c->graph_cache);
+  if (!gc) return;
+  for (auto& kv : gc->execs) gc->retired.push_back(kv.second);
+  gc->execs.clear();
+}
+
 bool dims_ok(const int64_t d[3]) {
   if (d[0] < 1 || d[1] < 1 || d[2] < 1) return false;
   if (d[0] > (1 << 30) || d[1] > (1 << 30) || d[2] > (1 << 30)) return false;
@@ -58,25 +68,27 @@ bool dims_ok(const int64_t d[3]) {
   return n < 1099511627776.0;   // 2^40
 }
 
+// Grow the workspace to at least `bytes`.  The old block may still be read
+// by work queued on any stream, and the cached sweep graphs hold its
+// address, so neither is released here: both are retired (kept alive) and
+// freed by mtk_graph_reset or mtk_destroy, which synchronise the device.
+// Growth therefore never waits for the device.  Sizes grow at least 1.5x,
+// so the retired blocks add up to less than twice the live one.
 mtk_status ensure_ws(mtk_ctx* c, size_t bytes, hipStream_t st) {
+  (void)st;
   if (bytes <= c->ws_bytes) return MTK_OK;
-  // The old workspace may still be in use by queued work, and every cached
-  // sweep graph holds its address.
-  if (c->ws) {
-    HIP_OR_FAIL(c, hipStreamSynchronize(st));
-    HIP_OR_FAIL(c, hipDeviceSynchronize());
-    mtk_status gs = mtk_graph_reset(c);
-    if (gs != MTK_OK) return gs;
-    HIP_OR_FAIL(c, hipFree(c->ws));
-    c->ws = nullptr;
-    c->ws_bytes = 0;
-  }
   size_t want = std::max<size_t>(bytes, 1 << 20);
-  if (hipMalloc(&c->ws, want) != hipSuccess) {
+  if (c->ws) want = std::max(want, c->ws_bytes + c->ws_bytes / 2);
+  void* nw = nullptr;
+  if (hipMalloc(&nw, want) != hipSuccess) {
     (void)hipGetLastError();
-    c->ws = nullptr;
     return fail(c, MTK_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
   }
+  if (c->ws) {
+    c->retired_ws.push_back(c->ws);
+    retire_graphs(c);
+  }
+  c->ws = nw;
   c->ws_bytes = want;
   return MTK_OK;
 }
@@ -174,12 +186,18 @@ mtk_status mtk_create(mtk_ctx** ctx, int device) {
 mtk_status mtk_graph_reset(mtk_ctx* c) {
   if (!c) return MTK_EINVAL;
   GraphCache* gc = static_cast<GraphCache*>(c->graph_cache);
-  if (!gc) return MTK_OK;
+  (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  for (auto& kv : gc->execs) (void)hipGraphExecDestroy(kv.second);
-  for (hipGraph_t g : gc->graphs) (void)hipGraphDestroy(g);
-  gc->execs.clear();
-  gc->graphs.clear();
+  if (gc) {
+    for (auto& kv : gc->execs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraphExec_t e : gc->retired) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : gc->graphs) (void)hipGraphDestroy(g);
+    gc->execs.clear();
+    gc->retired.clear();
+    gc->graphs.clear();
+  }
+  for (void* p : c->retired_ws) (void)hipFree(p);
+  c->retired_ws.clear();
   return MTK_OK;
 }
 
@@ -539,6 +557,7 @@ mtk_status als_run(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], dou
     hipError_t e = mtk::launch_sumsq(X->data, X->fmt, X->slice_exp, X->dims, c->d_fit, scratch, st);
     if (e != hipSuccess) return hip_fail(c, e, "norm launch");
     HIP_OR_FAIL(c, hipMemcpyAsync(acc, c->d_fit, sizeof(acc), hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(c, hipStreamSynchronize(st));   // acc is host memory written by the copy
     if ((s = enqueue_initial_grams(c, X, factors, (int)R, prec, st)) != MTK_OK) return s;
     const double* ip_dev = mtk::solve_ip(maxdim, (int)R, sweep_solve_ws(c, X->dims, (int)R, prec));
     const double nx2 = acc[1];

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/mttkrp.h"
 
@@ -161,6 +162,7 @@ struct mtk_ctx {
   int* d_status = nullptr;        // sticky status word + reduction counters (kStatusWords ints)
   double* d_fit = nullptr;        // fit accumulators
   std::string last_error;
+  std::vector<void*> retired_ws;  // outgrown workspace blocks (freed by mtk_graph_reset / mtk_destroy)
   void* graph_cache = nullptr;    // als_sweep graph cache (see api.hip)
   hipStream_t side = nullptr;     // second stream of the captured sweep (factorisation)
   hipEvent_t fork_ev[3] = {nullptr, nullptr, nullptr};

@@ -706,6 +706,7 @@ hipError_t dispatch_nt(const KArgs& a, const ContractPlan& p, hipStream_t st) {
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+constexpr int64_t kMaxGridX = 0x7fffffff;
 
 // Plan limits (compile-time so a build can be tuned without code changes):
 // widest per-lane reduction run for FP32 / bf16x3, and the workgroup count
@@ -820,6 +821,8 @@ hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void
                            const int32_t* slice_exp, const float* frag_src, const float* weight,
                            float* out, void* ws, hipStream_t st, const FactorArgs* job) {
   if (job && (job->R > kJobMaxRank || p.ntw > 2)) return hipErrorInvalidValue;
+  // One-dimensional grids (contraction, reduction) must fit gridDim.x.
+  if (p.grid() + 1 > kMaxGridX || cdiv((int64_t)p.nM * p.R, 32) > kMaxGridX) return hipErrorInvalidConfiguration;
   KArgs a{};
   a.job_on = job ? 1 : 0;
   if (job) a.job = *job;

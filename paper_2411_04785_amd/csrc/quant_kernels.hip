@@ -10,6 +10,8 @@
 #include "mtk_internal.h"
 #include "fp8_codec.h"
 
+#include <algorithm>
+
 namespace mtk {
 namespace {
 
@@ -56,41 +58,47 @@ __global__ __launch_bounds__(256) void slice_encode_kernel(const float* __restri
 }
 
 // qt[(i*K + k)*J + j] = q[(i*J + j)*K + k]: each mode-1 slice transposed,
-// through a 64 x 64 byte tile in LDS.  Block (k tile, j tile, slice).
-__global__ __launch_bounds__(256) void slice_transpose_kernel(const uint8_t* __restrict__ q, int64_t J, int64_t K,
-                                                              uint8_t* __restrict__ qt) {
+// through a 64 x 64 byte tile in LDS.  Tile t = (slice i, j tile, k tile),
+// k tile fastest; the workgroups stride over the I * nj * nk tiles, so no
+// grid dimension grows with I.
+__global__ __launch_bounds__(256) void slice_transpose_kernel(const uint8_t* __restrict__ q, int64_t I, int64_t J,
+                                                              int64_t K, uint8_t* __restrict__ qt) {
   __shared__ uint8_t tile[64][65];
-  const int64_t i = blockIdx.z;
-  const int64_t j0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64;
+  const int64_t nj = (J + 63) / 64, nk = (K + 63) / 64;
   const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 16;
-  {
-    const int64_t j = j0 + r;
-    const uint8_t* src = q + (i * J + j) * K + k0 + c0;
-    const bool full = j < J && k0 + c0 + 16 <= K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
-    if (full) {
-      const uint4 u = *reinterpret_cast<const uint4*>(src);
-      const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+  for (int64_t t = blockIdx.x; t < I * nj * nk; t += gridDim.x) {
+    const int64_t i = t / (nj * nk);
+    const int64_t jt = (t - i * nj * nk) / nk;
+    const int64_t j0 = jt * 64, k0 = (t - i * nj * nk - jt * nk) * 64;
+    {
+      const int64_t j = j0 + r;
+      const uint8_t* src = q + (i * J + j) * K + k0 + c0;
+      const bool full = j < J && k0 + c0 + 16 <= K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
+      if (full) {
+        const uint4 u = *reinterpret_cast<const uint4*>(src);
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
-      for (int b = 0; b < 16; ++b) tile[r][c0 + b] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
-    } else {
-      for (int b = 0; b < 16; ++b) tile[r][c0 + b] = (j < J && k0 + c0 + b < K) ? src[b] : 0;
+        for (int b = 0; b < 16; ++b) tile[r][c0 + b] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
+      } else {
+        for (int b = 0; b < 16; ++b) tile[r][c0 + b] = (j < J && k0 + c0 + b < K) ? src[b] : 0;
+      }
     }
-  }
-  __syncthreads();
-  {
+    __syncthreads();
     const int64_t k = k0 + r;
-    if (k >= K) return;
-    uint8_t* dst = qt + (i * K + k) * J + j0 + c0;
-    const bool full = j0 + c0 + 16 <= J && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
-    if (full) {
-      uint32_t w[4] = {0, 0, 0, 0};
+    if (k < K) {
+      uint8_t* dst = qt + (i * K + k) * J + j0 + c0;
+      const bool full = j0 + c0 + 16 <= J && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0);
+      if (full) {
+        uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int b = 0; b < 16; ++b) w[b >> 2] |= (uint32_t)tile[c0 + b][r] << (8 * (b & 3));
-      *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
-    } else {
-      for (int b = 0; b < 16; ++b)
-        if (j0 + c0 + b < J) dst[b] = tile[c0 + b][r];
+        for (int b = 0; b < 16; ++b) w[b >> 2] |= (uint32_t)tile[c0 + b][r] << (8 * (b & 3));
+        *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+      } else {
+        for (int b = 0; b < 16; ++b)
+          if (j0 + c0 + b < J) dst[b] = tile[c0 + b][r];
+      }
     }
+    __syncthreads();                  // the tile is refilled by the next item
   }
 }
 
@@ -104,8 +112,9 @@ hipError_t launch_quantize_slices(const float* x, int64_t I, int64_t J, int64_t 
   const int64_t blocks = (n / 4 + 255) / 256 + 1;
   hipLaunchKernelGGL(slice_encode_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, JK, n, exps, q);
   if (qt) {
-    hipLaunchKernelGGL(slice_transpose_kernel, dim3((unsigned)((K + 63) / 64), (unsigned)((J + 63) / 64), (unsigned)I),
-                       dim3(256), 0, st, q, J, K, qt);
+    const int64_t tiles = I * ((J + 63) / 64) * ((K + 63) / 64);
+    hipLaunchKernelGGL(slice_transpose_kernel, dim3((unsigned)std::min<int64_t>(tiles, (int64_t)1 << 20)), dim3(256), 0,
+                       st, q, I, J, K, qt);
   }
   return hipGetLastError();
 }

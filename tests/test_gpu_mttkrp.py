@@ -257,3 +257,32 @@ def test_dimtree_deterministic_and_rejects(ctx):
     assert np.array_equal(a, b)
     with pytest.raises(MtkError):
         ctx.mttkrp_dimtree(Xd, fd, 2, "fp32")
+
+
+def test_skewed_slices_beyond_grid_y(ctx):
+    # I = 70000 slices: more than a y or z grid dimension holds.  The fit and
+    # the transposed FP8 copy stride over (slice, tile) items in one grid
+    # dimension; every path must still match the oracle.
+    from gpu_util import dev, host, rel
+    g = np.random.default_rng(70)
+    X = (g.standard_normal((70000, 8, 8)) * np.power(10.0, g.uniform(-2, 2, (70000, 1, 1)))).astype(np.float32)
+    facs = [g.standard_normal((d, 8)).astype(np.float32) for d in X.shape]
+    Xd, fd = dev(X), [dev(f) for f in facs]
+    for mode in range(3):
+        for prec in ("fp32", "bf16x3"):
+            _say("skewed 70000x8x8", prec, mode)
+            got = host(ctx.mttkrp(Xd, fd, mode, prec))
+            assert rel(got, oracle.mttkrp(X, facs, mode)) <= TOL[prec], (prec, mode)
+    q, e, qt = ctx.quantize_fp8(Xd, transposed=True)
+    qo, eo = oracle.quantize_slices_e4m3(X)
+    assert np.array_equal(host(e), eo) and np.array_equal(host(q), qo)
+    assert np.array_equal(host(qt), np.ascontiguousarray(np.transpose(qo, (0, 2, 1))))
+    Xq = oracle.dequantize_slices_e4m3(qo, eo)
+    for mode in range(3):
+        got = host(ctx.mttkrp(q, fd, mode, "fp8", slice_exp=e, X_t=qt))
+        assert rel(got, oracle.mttkrp(Xq, facs, mode)) <= 5e-3, mode
+    lam = np.array([1.0, -0.5, 2.0, 0.25, 1.5, 0.75, -1.25, 0.5])
+    got = ctx.fit(Xd, fd, dev(lam))
+    assert abs(got - oracle.fit(X, facs, lam, slices_per_chunk=4096)) <= 1e-10
+    got = ctx.fit(q, fd, dev(lam), slice_exp=e)
+    assert abs(got - oracle.fit(Xq, facs, lam, slices_per_chunk=4096)) <= 1e-10
