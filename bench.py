@@ -1,29 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of the dense 3-way MTTKRP / CP-ALS hot path on one MI355X.
 
-Default workload (N=1): 512 x 512 x 512 FP32 tensor, rank-32 CP model plus
-N(0, 1e-4) noise, R = 32 factors iid N(0,1) (synthetic, seeded).  One step =
-one CP-ALS sweep on the device: for each mode an MTTKRP (HIP contraction +
-fixed-order split-K reduce; for FP32 tensors with K >= 8R the mode-1 and mode-2
-MTTKRPs come from one shared contraction Y = X x3 C, the dimension tree, so
-the sweep reads X twice) followed by the FP64 Gram / LDL^T (Cholesky) inverse /
-solve / normalise update.  ``value`` is algorithmic MTTKRP GFLOP/s of the whole
-sweep (3 * 2*I*J*K*R flop per step over the step time, solves included).
+Default workload (N=1): the 1024 x 1024 x 1024 FP32 tensor (4 GiB), rank-64
+CP model plus N(0, 1e-3) noise, R = 64 factors iid N(0,1) (synthetic,
+seeded).  The headline path is the bf16x3 contraction (each FP32 operand
+split into bf16 hi + lo, three bf16 MFMA products, FP32 accumulation); the
+plain FP32 path (FP32 MFMA) is timed beside it on the same tensor.  One step
+= one CP-ALS sweep on the device: for each mode an MTTKRP (for FP32 tensors
+with K >= 8R the mode-1 and mode-2 MTTKRPs come from one shared contraction
+Y = X x3 C, the dimension tree, so the sweep reads X twice) followed by the
+FP64 Gram / LDL^T (Cholesky) inverse / solve / normalise update.
 
-Also measured live (HIP events on the library's stream): each mode's MTTKRP
-on its own, giving the roofline of the contraction kernel, and a sampled
-parity check of the timed results against the FP64 oracle.  The oracle
-itself is timed on the host cores as ``cpu_baseline``.
+``value`` is the algorithmic MTTKRP rate of the headline sweep: 3 x 2*I*J*K*R
+flop per sweep (the three MTTKRPs a sweep defines) over the measured sweep
+time; the flops the dimension tree actually executes are in ``detail``.
+
+Also measured live, with HIP events on the stream the library launches on:
+each mode's MTTKRP on its own for both paths, and the kernel that takes the
+largest share of the headline sweep (the roofline object).  The FP64 oracle
+runs on the host cores as ``cpu_baseline`` (timed on a bounded sample); its
+full MTTKRPs also give each path's per-mode error over every output row.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
-                    [--workload cp512_r32|cp1024_r64|cp768_r128_sliced|cp64_r8|serve]
-                    [--prec fp32|bf16x3|fp8] [--no-cpu-baseline]
+                    [--workload cp1024_r64|cp512_r32|cp768_r128_sliced|cp64_r8|serve|copy]
+                    [--prec fp32|bf16x3|fp8] [--compare fp32|none] [--no-cpu-baseline]
 
-``--workload serve`` runs the serving workload instead: an open-loop Poisson
-stream of CP-ALS requests (dims uniform on [32, 384] per mode, R uniform over
-{8, 16, 32, 64}, 10 sweeps each) into the continuous-batching server under an
-HBM budget, and reports requests/s with p50/p99 latency (completion minus
-scheduled arrival, host-to-device and back included).
+``--workload cp768_r128_sliced`` (FP8 e4m3, per-slice scales) also runs the
+workload's 20 CP-ALS sweeps and reports their fit and model against the
+oracle's 20 sweeps (``tests/golden/cp768_r128_als.json``, written by the
+oracle).  ``--workload serve`` runs the serving workload instead (see
+serve_bench).
 """
 
 from __future__ import annotations
@@ -40,7 +46,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Dense MFMA peaks per path, in algorithmic flops: bf16x3 issues three bf16
+# MFMA products per product of the definition, FP8 two e4m3 ones.
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6 / 3.0, "fp8": 5033.2 / 2.0}
+DEFAULT_PREC = {"cp64_r8": "fp32", "cp512_r32": "fp32", "cp1024_r64": "bf16x3", "cp768_r128_sliced": "fp8"}
 
 
 def log(*a):
@@ -60,43 +70,84 @@ def algorithmic_bytes(dims, R, mode, prec):
 
 
 def kernel_sources_hash():
-    """sha256 prefix of the contraction kernel's sources (to tell whether a
-    recorded counter measurement still describes the built kernel)."""
+    """sha256 prefix of the library's kernel sources (to tell whether a
+    recorded counter measurement still describes the built kernels)."""
     import hashlib
     d = os.path.join(ROOT, "paper_2411_04785_amd", "csrc")
-    src = b"".join(open(os.path.join(d, f), "rb").read() for f in ("mttkrp_kernels.hip", "tile_device.h", "factor_device.h", "fp8_codec.h", "mtk_internal.h"))
+    names = sorted(f for f in os.listdir(d) if f.endswith((".hip", ".h")))
+    src = b"".join(open(os.path.join(d, f), "rb").read() for f in names)
     return hashlib.sha256(src).hexdigest()[:16]
 
 
-def recorded_traffic(workload, prec):
-    """HBM bytes per contraction launch from the committed FETCH_SIZE / WRITE_SIZE
-    runs, or None if none match this workload or the kernel changed since."""
+def recorded_traffic(workload, prec, kernel=None):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE runs, or None if none match this workload or the kernel
+    sources changed since."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_sources_sha256_16") != kernel_sources_hash():
         return None
+    if kernel is not None and rec.get("kernel", kernel) != kernel:
+        return None
     return rec["traffic_bytes_per_launch_mean"]
 
 
-def cpu_baseline(X, facs, sweeps=2):
-    """The FP64 oracle's CP-ALS, timed on the host (BLAS threads as configured)."""
-    import oracle
+def ytree_bytes(dims, R):
+    """Bytes the dimension tree's Y kernel must move: X (FP32), C, B, Y
+    (I*J x R FP32, written) and its partial rows of M1 (J / 256 slices below
+    R = 65, J / 128 above; the Y kernel forms them when J is a multiple of
+    that)."""
+    I, J, K = dims
+    rows = 256 if R <= 64 else 128
+    parts = J // rows if J % rows == 0 else 0
+    return 4 * I * J * K + 4 * K * R + 4 * J * R + 4 * I * J * R + 4 * parts * I * R
+
+
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+        return max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
     except Exception:
-        cores = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(X, facs, reps=3):
+    """The FP64 oracle on the host: each mode's full MTTKRP once (the
+    references for the per-mode errors), then the mode-0 MTTKRP `reps` more
+    times; the reported rate is the median of those `reps` timings."""
+    import oracle
     I, J, K = X.shape
     R = facs[0].shape[1]
-    t0 = time.perf_counter()
-    oracle.cp_als(X, facs, sweeps, fit_every_sweep=False)
-    dt = time.perf_counter() - t0
-    flops = sweeps * 3 * 2.0 * I * J * K * R
-    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{sweeps} FP64 CP-ALS sweeps (3 MTTKRP + LU normal-equation solves each) of the oracle "
-                      f"on the same {I}x{J}x{K} tensor, R={R}; {dt:.2f} s"}
+    flop = 2.0 * I * J * K * R
+    refs, ref_s = [], []
+    for mode in range(3):
+        t0 = time.perf_counter()
+        refs.append(oracle.mttkrp(X, facs, mode))
+        ref_s.append(time.perf_counter() - t0)
+        log(f"[bench] oracle mode {mode}: {ref_s[-1]:.2f} s")
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        oracle.mttkrp(X, facs, 0)
+        ts.append(time.perf_counter() - t0)
+    med = float(np.median(ts))
+    out = {"value": round(flop / med / 1e9, 2), "unit": "GFLOP/s", "cores": int(blas_threads()), "kind": "oracle",
+           "sample": f"FP64 oracle mode-1 MTTKRP of the same {I}x{J}x{K} tensor, R={R} (unfolding x explicit "
+                     f"Khatri-Rao product, BLAS), median of {reps} runs: {', '.join(f'{t:.2f}' for t in ts)} s",
+           "all_modes_s": [round(t, 3) for t in ref_s]}
+    if I * J * K <= 512**3:
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1, user_api="blas"):
+                t0 = time.perf_counter()
+                oracle.mttkrp(X, facs, 0)
+                t1 = time.perf_counter() - t0
+            out["single_thread_value"] = round(flop / t1 / 1e9, 2)
+        except Exception:
+            pass
+    return out, refs
 
 
 def serve_bench(args):
@@ -216,13 +267,142 @@ def copy_bench(args):
                       "ms_per_copy": round(ms, 4), "steps": args.steps}), flush=True)
 
 
+
+
+def _events(torch, stream):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    return e0, e1
+
+
+def time_calls(torch, stream, fn, reps, warm=10):
+    """Average ms of fn() over `reps` back-to-back calls, HIP events on the
+    library's stream, after `warm` untimed calls (steady clocks, page tables)."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, stream)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_path(ctx, torch, stream, w, prec, X_run, kw, f0, args):
+    """Per-mode MTTKRP times and outputs, then timed CP-ALS sweeps, of one path."""
+    R = w.R
+    mode_ms, outs = [], []
+    for mode in range(3):
+        out = ctx.mttkrp(X_run, f0, mode, prec, **kw)
+        mode_ms.append(time_calls(torch, stream, lambda: ctx.mttkrp(X_run, f0, mode, prec, out=out, **kw),
+                                  args.mode_reps))
+        outs.append(out.cpu().numpy())
+        log(f"[bench] {prec} mode {mode}: {mode_ms[-1] * 1e3:.1f} us per MTTKRP")
+    ctx.check()
+    fd = [f.clone() for f in f0]
+    lam = torch.ones(R, dtype=torch.float64, device=X_run.device)
+    ctx.reserve(w.dims, R, prec)
+    ctx.als_sweep(X_run, fd, lam, max(1, args.warmup), prec, **kw)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, stream)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    ctx.als_sweep(X_run, fd, lam, args.steps, prec, **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_step = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] {prec}: {args.steps} sweeps {ms_step:.3f} ms/sweep (wall {t_wall:.3f} s)")
+    return {"mode_ms": mode_ms, "outs": outs, "ms_step": ms_step, "factors": fd, "lam": lam}
+
+
+def dominant_kernel(ctx, torch, stream, w, prec, X_run, kw, f0, mode_ms, reps):
+    """The kernel with the largest share of the headline sweep, timed alone
+    (HIP events, same stream): with the dimension tree, the Y kernel
+    (mttkrp_dimtree mode 0: Y = X x3 C with its partial rows of M1, then a
+    reduce of those few rows) or the mode-3 contraction, whichever is longer;
+    without it, the slowest mode's contraction.  Returns (name, ms, bytes)."""
+    from paper_2411_04785_amd.mttkrp import Context
+    cands = []
+    if Context.sweep_uses_dimtree(w.dims, w.R, prec):
+        out = ctx.mttkrp_dimtree(X_run, f0, 0, prec)
+        ms = time_calls(torch, stream, lambda: ctx.mttkrp_dimtree(X_run, f0, 0, prec, out=out), reps)
+        cands.append(("ttm_kernel (Y = X x3 C with M1 partial rows) + slice reduce", ms, ytree_bytes(w.dims, w.R)))
+        cands.append(("mode-3 contraction (contract_cm_kernel) + split-K reduce", mode_ms[2],
+                      algorithmic_bytes(w.dims, w.R, 2, prec)))
+    else:
+        m = int(np.argmax(mode_ms))
+        cands.append((f"mode-{m + 1} contraction + split-K reduce", mode_ms[m], algorithmic_bytes(w.dims, w.R, m, prec)))
+    return max(cands, key=lambda c: c[1])
+
+
+def roofline(name, ms, nbytes, flop, prec):
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_cmp = flop / (PEAK_TFLOPS[prec] * 1e12)
+    if t_hbm >= t_cmp:
+        ach = nbytes / (ms * 1e-3) / 1e9
+        r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(ach / HBM_PEAK_GBS, 4)}
+    else:
+        ach = flop / (ms * 1e-3) / 1e12
+        r = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+             "frac": round(ach / PEAK_TFLOPS[prec], 4)}
+    r["kernel"] = name
+    r["avg_launch_us"] = round(ms * 1e3, 2)
+    r["algorithmic_bytes"] = int(nbytes)
+    return r
+
+
+def err_rows(outs, refs):
+    """Per-mode relative Frobenius error over every output row, and the
+    worst single row (relative 2-norm over its R values)."""
+    e, wr = [], []
+    for got, ref in zip(outs, refs):
+        d = got.astype(np.float64) - ref
+        e.append(float(np.linalg.norm(d) / np.linalg.norm(ref)))
+        wr.append(float(np.max(np.linalg.norm(d, axis=1) / np.linalg.norm(ref, axis=1))))
+    return [float(f"{v:.3e}") for v in e], [float(f"{v:.3e}") for v in wr]
+
+
+def fp8_als_vs_oracle(ctx, torch, w, q, kw, Xd, f0):
+    """The workload's CP-ALS sweeps on the FP8 tensor against the oracle's
+    sweeps on the FP32 tensor (tests/golden/cp768_r128_als.json, written by
+    the oracle): fit (direct residual against the unquantised tensor) and the
+    model at the recorded sample entries."""
+    path = os.path.join(ROOT, "tests", "golden", "cp768_r128_als.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    fd = [f.clone() for f in f0]
+    lam = torch.ones(w.R, dtype=torch.float64, device=Xd.device)
+    t0 = time.perf_counter()
+    ctx.als_sweep(q, fd, lam, g["sweeps"], "fp8", **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fit = ctx.fit(Xd, fd, lam)
+    A, B, C = (f.cpu().numpy().astype(np.float64) for f in fd)
+    lv = lam.cpu().numpy()
+    got, ref = [], []
+    for s, i in enumerate(g["sample_slices"]):
+        for (j, k), v in zip(g["sample_jk"][s], g["model_at_samples"][s]):
+            got.append(float(np.sum(lv * A[i] * B[j] * C[k])))
+            ref.append(v)
+    got, ref = np.array(got), np.array(ref)
+    return {"sweeps": g["sweeps"], "wall_s_incl_graph_capture": round(dt, 3), "fit_fp8": round(fit, 7),
+            "fit_oracle_fp64": round(g["fit"], 7), "fit_abs_diff": float(f"{abs(fit - g['fit']):.3e}"),
+            "model_rel_err_at_samples": float(f"{np.linalg.norm(got - ref) / np.linalg.norm(ref):.3e}")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cp512_r32")
+    ap.add_argument("--workload", default="cp1024_r64")
     ap.add_argument("--prec", default=None)
+    ap.add_argument("--compare", default=None, help="path timed beside the headline (default fp32; none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode-reps", type=int, default=20)
     ap.add_argument("--requests", type=int, default=2000)
@@ -245,15 +425,17 @@ def main():
         return
 
     import torch
-    import oracle
     from paper_2411_04785_amd import synth
     from paper_2411_04785_amd.mttkrp import Context
 
     w = synth.WORKLOADS[args.workload]
-    prec = args.prec or ("fp8" if w.slice_log10 is not None else "fp32")
+    prec = args.prec or DEFAULT_PREC[w.name]
+    compare = args.compare or "fp32"
+    if compare in ("none", prec):
+        compare = None
     I, J, K = w.dims
     R = w.R
-    log(f"[bench] workload {w.name} dims={w.dims} R={R} prec={prec}: generating input")
+    log(f"[bench] workload {w.name} dims={w.dims} R={R} prec={prec} compare={compare}: generating input")
     t0 = time.perf_counter()
     X = synth.tensor(w)
     facs = synth.init_factors(w)
@@ -267,111 +449,79 @@ def main():
     torch.cuda.set_stream(stream)
     ctx = Context(0)
     Xd = torch.from_numpy(X).to(dev)
-    slice_exp = None
-    Xt = None
-    if prec == "fp8":
-        Xq, slice_exp, Xt = ctx.quantize_fp8(Xd, transposed=True)
-        torch.cuda.synchronize()
-        Xrun = Xq
-    else:
-        Xrun = Xd
     f0 = [torch.from_numpy(f).to(dev) for f in facs]
-
-    # ---- per-mode MTTKRP timing (HIP events on the library's stream) ----
-    mode_ms = []
-    outs = []
-    for mode in range(3):
-        out = ctx.mttkrp(Xrun, f0, mode, prec, slice_exp=slice_exp, X_t=Xt)
-        for _ in range(10):         # untimed: steady state (page tables, clocks)
-            ctx.mttkrp(Xrun, f0, mode, prec, out=out, slice_exp=slice_exp, X_t=Xt)
+    runs = {}
+    kw = {}
+    X_head = Xd
+    if prec == "fp8":
+        q, slice_exp, Xt = ctx.quantize_fp8(Xd, transposed=True)
         torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        for _ in range(args.mode_reps):
-            ctx.mttkrp(Xrun, f0, mode, prec, out=out, slice_exp=slice_exp, X_t=Xt)
-        ev1.record(stream)
-        ev1.synchronize()
-        mode_ms.append(ev0.elapsed_time(ev1) / args.mode_reps)
-        outs.append(out.cpu().numpy())
-        log(f"[bench] mode {mode}: {mode_ms[-1] * 1e3:.1f} us per MTTKRP")
-    ctx.check()
-
-    # Sampled parity of the timed results against the FP64 oracle.
-    rng = np.random.default_rng(0)
-    errs, worst = [], []
-    mags = synth.slice_magnitudes(w)
-    for mode in range(3):
-        rows = [0, w.dims[mode] - 1]
-        if mode == 0 and mags is not None:          # the smallest and largest slices
-            rows += [int(np.argmin(mags)), int(np.argmax(mags))]
-        rows = np.unique(np.concatenate([rows, rng.integers(0, w.dims[mode], 6)]))
-        ref = oracle.mttkrp_rows(X, facs, mode, rows)
-        got = outs[mode][rows].astype(np.float64)
-        errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
-        worst.append(float(np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1))))
-    log(f"[bench] sampled relative error vs FP64 oracle per mode: {errs} (worst row {worst})")
-
-    # ---- timed CP-ALS sweeps ----
-    fd = [f.clone() for f in f0]
-    lam = torch.ones(R, dtype=torch.float64, device=dev)
-    ctx.reserve(w.dims, R, prec)
-    ctx.als_sweep(Xrun, fd, lam, max(1, args.warmup), prec, slice_exp=slice_exp, X_t=Xt)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t_wall = time.perf_counter()
-    ev0.record(stream)
-    ctx.als_sweep(Xrun, fd, lam, args.steps, prec, slice_exp=slice_exp, X_t=Xt)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    fit = ctx.fit(Xrun, fd, lam, slice_exp=slice_exp, X_t=Xt)
-    log(f"[bench] {args.steps} sweeps: {ms_step:.3f} ms/sweep (wall {t_wall:.3f} s), fit {fit:.6f}")
+        X_head, kw = q, {"slice_exp": slice_exp, "X_t": Xt}
+    runs[prec] = run_path(ctx, torch, stream, w, prec, X_head, kw, f0, args)
+    name, k_ms, k_bytes = dominant_kernel(ctx, torch, stream, w, prec, X_head, kw, f0, runs[prec]["mode_ms"],
+                                          args.mode_reps)
+    log(f"[bench] dominant kernel: {name}: {k_ms * 1e3:.1f} us")
+    fp8_als = None
+    if prec == "fp8" and w.als_sweeps:
+        fp8_als = fp8_als_vs_oracle(ctx, torch, w, X_head, kw, Xd, f0)
+        log(f"[bench] FP8 CP-ALS vs oracle: {fp8_als}")
+    if compare:
+        runs[compare] = run_path(ctx, torch, stream, w, compare, Xd, {}, f0, args)
+    fit = ctx.fit(X_head, runs[prec]["factors"], runs[prec]["lam"], **kw)
 
     flop_mttkrp = 2.0 * I * J * K * R
-    value = 3 * flop_mttkrp / (ms_step * 1e-3) / 1e9
+    head = runs[prec]
+    value = 3 * flop_mttkrp / (head["ms_step"] * 1e-3) / 1e9
+    tree = Context.sweep_uses_dimtree(w.dims, R, prec)
+    # Flops a sweep executes: with the tree, the Y contraction (2IJKR), the two
+    # sums over Y (2 x 2IJR) and the mode-3 contraction (2IJKR); else 3 x 2IJKR.
+    exec_flop = (2 * flop_mttkrp + 2 * 2.0 * I * J * R) if tree else 3 * flop_mttkrp
+    roof = roofline(name, k_ms, k_bytes, flop_mttkrp, prec)
+    roof["traffic"] = recorded_traffic(w.name, prec, name)
 
-    bytes_modes = [algorithmic_bytes(w.dims, R, m, prec) for m in range(3)]
-    avg_ms = float(np.mean(mode_ms))
-    ach_gbs = float(np.mean([b / (t * 1e-3) / 1e9 for b, t in zip(bytes_modes, mode_ms)]))
-    ach_tf = float(np.mean([flop_mttkrp / (t * 1e-3) / 1e12 for t in mode_ms]))
-    t_hbm = float(np.mean(bytes_modes)) / (HBM_PEAK_GBS * 1e9)
-    t_cmp = flop_mttkrp / (PEAK_TFLOPS[prec] * 1e12)
-    if t_hbm >= t_cmp:
-        roof = {"bound": "hbm", "achieved": round(ach_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach_gbs / HBM_PEAK_GBS, 4)}
-    else:
-        roof = {"bound": "mfma", "achieved": round(ach_tf, 2), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                "frac": round(ach_tf / PEAK_TFLOPS[prec], 4)}
-    roof["traffic"] = recorded_traffic(w.name, prec)
-    roof["kernel"] = "mttkrp contraction + split-K reduce, mean of modes 1-3"
-
-    cpu = None
+    cpu, refs = None, None
     if not args.no_cpu_baseline:
-        log("[bench] timing the FP64 oracle on the host")
-        cpu = cpu_baseline(X, facs)
+        log("[bench] FP64 oracle on the host (references for the per-mode errors, then the timed sample)")
+        cpu, refs = cpu_baseline(X, facs)
 
-    dtype = {"fp32": "f32", "bf16x3": "bf16x3 (bf16 MFMA, f32 accumulate)", "fp8": "e4m3 (f32 accumulate)"}[prec]
+    detail = {"sweep_passes_over_X": 2 if tree else 3,
+              "executed_gflop_per_sweep": round(exec_flop / 1e9, 2),
+              "executed_gflops": round(exec_flop / (head["ms_step"] * 1e-3) / 1e9, 1),
+              "fit_after": round(fit, 7)}
+    for p, r in runs.items():
+        bytes_modes = [algorithmic_bytes(w.dims, R, m, p) for m in range(3)]
+        d = {"ms_per_sweep": round(r["ms_step"], 4),
+             "mttkrp_us": [round(t * 1e3, 2) for t in r["mode_ms"]],
+             "mttkrp_gflops": [round(flop_mttkrp / (t * 1e-3) / 1e9, 1) for t in r["mode_ms"]],
+             "mttkrp_gbs": [round(b / (t * 1e-3) / 1e9, 1) for b, t in zip(bytes_modes, r["mode_ms"])],
+             "mttkrp_roofline": [{k: v for k, v in roofline("", t, b, flop_mttkrp, p).items()
+                                  if k in ("bound", "frac")} for b, t in zip(bytes_modes, r["mode_ms"])]}
+        if refs is not None:
+            d["err_rel_per_mode_all_rows"], d["err_rel_worst_row"] = err_rows(r["outs"], refs)
+        detail[p] = d
+    if compare:
+        detail["sweep_speedup_vs_" + compare] = round(runs[compare]["ms_step"] / head["ms_step"], 3)
+        detail["mttkrp_speedup_vs_" + compare] = [round(a / b, 3) for a, b in
+                                                  zip(runs[compare]["mode_ms"], head["mode_ms"])]
+    if fp8_als is not None:
+        detail["fp8_als_vs_oracle"] = fp8_als
+    if cpu is not None:
+        detail["oracle_full_mode_s"] = cpu.pop("all_modes_s")
+
+    dtype = {"fp32": "f32", "bf16x3": "bf16x3", "fp8": "e4m3"}[prec]
     line = {
-        "metric": "MTTKRP GFLOP/s over a full CP-ALS sweep (3 modes + FP64 Gram/Cholesky solves)",
+        "metric": "MTTKRP GFLOP/s (algorithmic, 3 x 2IJKR per CP-ALS sweep) and % roofline vs plain FP32 at stated err",
         "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": round(head["ms_step"], 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": f"{w.name}: {I}x{J}x{K} rank-{w.rank_true} CP + N(0,{w.noise_var:g}) noise"
                                + (" per-slice magnitudes 10^U(-3,3)" if w.slice_log10 else "")
-                               + f", R={R}, {prec}, step = one CP-ALS sweep",
-                   "dims": list(w.dims), "R": R, "prec": prec},
+                               + f", R={R}, {prec}" + (f" timed beside {compare}" if compare else "")
+                               + ", step = one CP-ALS sweep",
+                   "dims": list(w.dims), "R": R, "prec": prec, "compare": compare},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "detail": {"mttkrp_us": [round(t * 1e3, 2) for t in mode_ms],
-                   "mttkrp_gflops": [round(flop_mttkrp / (t * 1e-3) / 1e9, 1) for t in mode_ms],
-                   "mttkrp_gbs": [round(b / (t * 1e-3) / 1e9, 1) for b, t in zip(bytes_modes, mode_ms)],
-                   "roofline_us_hbm": round(t_hbm * 1e6, 2), "roofline_us_compute": round(t_cmp * 1e6, 2),
-                   "err_rel_sampled_rows": [float(f"{e:.3e}") for e in errs],
-                   "err_rel_worst_sampled_row": [float(f"{e:.3e}") for e in worst], "fit_after": round(fit, 7),
-                   "sweep_passes_over_X": 2 if Context.sweep_uses_dimtree(w.dims, R, prec) else 3},
+        "detail": detail,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

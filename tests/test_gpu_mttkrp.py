@@ -174,19 +174,48 @@ def test_fp8_mttkrp(ctx, dims, R):
                 assert rel(plain, got) <= 1e-6
                 assert rel(plain, oracle.mttkrp(Xq, facs, mode)) <= 5e-3
         ref = oracle.mttkrp(X, facs, mode)
-        # 3e-2 against the unquantised tensor; on a small tensor the tensor's
-        # own e4m3 rounding (the oracle on the dequantised tensor) can pass
-        # that alone, and then the bar is that error plus the factor term.
         refq = oracle.mttkrp(Xq, facs, mode)
-        assert rel(got, ref) <= max(3e-2, rel(refq, ref) + 5e-3)
         # Against the dequantised tensor only the factor's two-term e4m3
-        # rounding (about 2^-8 relative per entry) remains.
+        # rounding (about 2^-8 relative per entry) remains.  (The stated 3e-2
+        # against the unquantised tensor is test_fp8_stated_bar below.)
         assert rel(got, refq) <= 5e-3
         # Worst output row: per-slice scaling keeps the 1e-3 slices as accurate
         # as the 1e3 ones (an underflowed slice would show an error near 1).
         if mode == 0:
             rr = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
             assert rr.max() <= 0.1
+
+
+# The stated FP8 bar, 3e-2 relative Frobenius error per mode against the
+# FP64 oracle on the *unquantised* tensor, asserted as stated.  Where the
+# e4m3 rounding of the tensor alone (the oracle on the dequantised tensor
+# against the oracle on the original) already exceeds 3e-2 the case cannot
+# meet the bar whatever the kernel does; those are expected failures, with
+# the measured floor as the reason.  (Per-slice scales leave a relative
+# rounding of about 2.65% rms per element; on small tensors whose slice
+# magnitudes span 10^6, a few slices dominate and the figure fluctuates
+# around it.)
+FP8_FLOOR_OVER_BAR = {
+    ((20, 24, 608), 32, 0): 3.035e-2,
+    ((12, 528, 20), 16, 2): 3.067e-2,
+}
+FP8_CASES = [(d, r, m) for d, r in [((40, 33, 50), 16), ((64, 64, 160), 128), ((31, 70, 130), 40),
+                                     ((20, 24, 608), 16), ((20, 24, 608), 32), ((18, 22, 600), 32),
+                                     ((12, 528, 20), 16)] for m in range(3)]
+
+
+@pytest.mark.parametrize("dims,R,mode", [
+    pytest.param(d, r, m, marks=pytest.mark.xfail(
+        strict=True, reason=f"e4m3 rounding of this tensor alone gives {FP8_FLOOR_OVER_BAR[(d, r, m)]:.3e} > 3e-2"))
+    if (d, r, m) in FP8_FLOOR_OVER_BAR else (d, r, m) for d, r, m in FP8_CASES])
+def test_fp8_stated_bar(ctx, dims, R, mode):
+    from gpu_util import dev, host, rel
+    X, facs = _sliced_case(dims, R, seed=11)
+    q, e, qt = ctx.quantize_fp8(dev(X), transposed=True)
+    got = host(ctx.mttkrp(q, [dev(f) for f in facs], mode, "fp8", slice_exp=e, X_t=qt))
+    err = rel(got, oracle.mttkrp(X, facs, mode))
+    _say("fp8 stated bar", dims, R, mode, f"{err:.4e}")
+    assert err <= 3e-2
 
 
 # --------------------------------------------------------- ABI errors ---
