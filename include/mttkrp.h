@@ -134,6 +134,23 @@ mtk_status mtk_quantize_fp8(mtk_ctx* ctx, const float* x, const int64_t dims[3],
 mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
                   int64_t R, int mode, int prec, float* out, void* stream);
 
+/* mttkrp without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels, plan and result (bit for bit)
+ * as mttkrp; the caller passes X, the factors and out as before.  The
+ * split-K partial slices and FP8 fragment codes go to a static device
+ * buffer of 64 MiB (one per device, held from library load until the
+ * process ends) instead of the context's workspace, and the call makes no
+ * hipMalloc, hipFree or other allocating call.  Nothing in the buffer needs
+ * to start at zero (every byte a launch reads it has written first).
+ * Every call on one device shares that device's buffer: calls that overlap
+ * on one device (any stream, any context) race and must be serialised by
+ * the caller.  Returns MTK_EUNSUPPORTED, enqueueing nothing, for a shape
+ * whose plan needs more than 64 MiB of scratch (e.g. 768^3 at R = 128 in
+ * FP32 / bf16x3 mode 2); every shape up to 1024^3 at R <= 64 fits. */
+mtk_status mttkrp_noalloc(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
+                          int64_t R, int mode, int prec, float* out, void* stream);
+
 /* Mode-0 or mode-1 MTTKRP by the dimension tree, the form als_sweep uses
  * for those two updates when mtk_sweep_uses_dimtree says so.  First
  * Y = X x_3 C, Y(i,j,r) = sum_k X(i,j,k) C(k,r) (an I*J x R FP32

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -139,6 +140,33 @@ size_t sweep_scratch_bytes(const int64_t dims[3], int R, int prec) {
   return sweep_contract_bytes(dims, R, prec) + mtk::solve_ws_bytes(maxdim, R) + dt;
 }
 
+// Scratch of mttkrp_noalloc: device memory that no call allocates.  Each
+// device the library runs on holds its own copy of this array from the
+// moment the code object is loaded until the process ends.  Host code must
+// not pass the array's name to a kernel (on the host it names a stand-in,
+// not device memory): mtk_create looks up the device address of the copy
+// on its device once and keeps it in g_scratch_ptr.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device` (looked up on
+// first use per device).
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -149,9 +177,12 @@ mtk_status mtk_create(mtk_ctx** ctx, int device) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MTK_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return MTK_EHIP;
+  void* scratch_ptr = nullptr;
+  if (scratch_address(device, &scratch_ptr) != hipSuccess) return MTK_EHIP;
   mtk_ctx* c = new (std::nothrow) mtk_ctx();
   if (!c) return MTK_ENOMEM;
   c->device = device;
+  c->scratch = scratch_ptr;
   const size_t status_bytes = mtk::kStatusWords * sizeof(int);
   if (hipMalloc(&c->d_status, status_bytes) != hipSuccess || hipMemset(c->d_status, 0, status_bytes) != hipSuccess) {
     delete c;
@@ -292,6 +323,31 @@ mtk_status mttkrp(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3]
   return mttkrp_impl(c, X, factors, (int)R, mode, prec, out, c->ws, st);
 }
 
+mtk_status mttkrp_noalloc(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], int64_t R, int mode,
+                          int prec, float* out, void* stream) {
+  if (!c) return MTK_EINVAL;
+  mtk_status s = check_tensor(c, X);
+  if (s != MTK_OK) return s;
+  if ((s = check_prec(c, X, prec)) != MTK_OK) return s;
+  if (mode < 0 || mode > 2) return fail(c, MTK_EINVAL, "mode must be 0, 1 or 2");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  if (!factors || !out) return fail(c, MTK_EINVAL, "NULL factors or out");
+  for (int m = 0; m < 3; ++m)
+    if (m != mode && !factors[m]) return fail(c, MTK_EINVAL, "NULL factor pointer");
+  if (!c->scratch) return fail(c, MTK_EHIP, "no device address for the static scratch");
+  // The same plan as mttkrp (so the same result, bit for bit); its
+  // partial slices and FP8 fragment codes must fit the static scratch.
+  const bool tr = mode == 2 && X->fmt == MTK_FP8_E4M3 && X->data_t != nullptr;
+  const ContractPlan p = mtk::make_plan(X->dims, (int)R, mode, prec, aligned16(tr ? X->data_t : X->data), tr);
+  const size_t need = mtk::contract_ws_bytes(p, prec);
+  if (need > kNoAllocScratchBytes)
+    return fail(c, MTK_EUNSUPPORTED, "mttkrp_noalloc: this shape needs " + std::to_string(need) +
+                                         " bytes of scratch, above the " + std::to_string(kNoAllocScratchBytes) +
+                                         "-byte static buffer (use mttkrp)");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  return mttkrp_impl(c, X, factors, (int)R, mode, prec, out, c->scratch, static_cast<hipStream_t>(stream));
+}
+
 mtk_status mttkrp_dimtree(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], int64_t R, int mode,
                           int prec, float* out, void* stream) {
   if (!c) return MTK_EINVAL;
@@ -359,7 +415,8 @@ mtk_status mtk_fit(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3
 }
 
 // One CP-ALS sweep (modes 0, 1, 2) enqueued on `st`, optionally followed by
-// the fit partial sums into c->d_fit.  M buffer and scratch come from ws.
+// the fit partial sums into c->d_fit.  M buffer and contraction scratch (cws)
+// come from ws.
 // Per mode: MTTKRP, then the update (LDL^T / Gauss-Jordan inverse of V from the Gram
 // matrices kept in the solve region, F = M V^{-1}, normalise, and the Gram
 // matrix of the new factor); for large R the factorisation runs on the
@@ -367,8 +424,8 @@ mtk_status mtk_fit(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3
 // in the solve region before the first sweep (enqueue_initial_grams).
 static void* sweep_solve_ws(mtk_ctx* c, const int64_t dims[3], int R, int prec) {
   const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
-  char* scratch = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
-  return scratch + sweep_contract_bytes(dims, R, prec);
+  char* cws = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
+  return cws + sweep_contract_bytes(dims, R, prec);
 }
 
 static void* sweep_dimtree_ws(mtk_ctx* c, const int64_t dims[3], int R, int prec) {
@@ -381,7 +438,7 @@ static void* sweep_dimtree_ws(mtk_ctx* c, const int64_t dims[3], int R, int prec
 // tree when the sweep uses one (dt_ws != nullptr; its split-K slices go to
 // the update unreduced), otherwise the direct contraction into M.
 static mtk_status sweep_mttkrp(mtk_ctx* c, const mtk_tensor* X, const float* const cf[3], int R, int n, int prec,
-                               float* M, void* scratch, void* dt_ws, hipStream_t st, mtk::MSlices* ms,
+                               float* M, void* cws, void* dt_ws, hipStream_t st, mtk::MSlices* ms,
                                const mtk::FactorArgs* job = nullptr) {
   *ms = mtk::MSlices{M, 1, 0};
   if (dt_ws && n < 2) {
@@ -390,7 +447,7 @@ static mtk_status sweep_mttkrp(mtk_ctx* c, const mtk_tensor* X, const float* con
     if (e != hipSuccess) return hip_fail(c, e, "dimension-tree launch");
     return MTK_OK;
   }
-  return mttkrp_impl(c, X, cf, R, n, prec, M, scratch, st, job);
+  return mttkrp_impl(c, X, cf, R, n, prec, M, cws, st, job);
 }
 
 static mtk_status enqueue_initial_grams(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], int R, int prec,
@@ -413,7 +470,7 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
                                 int prec, bool with_fit, hipStream_t st) {
   const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
   float* M = static_cast<float*>(c->ws);
-  void* scratch = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
+  void* cws = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
   void* solve_ws = sweep_solve_ws(c, X->dims, R, prec);
   void* dt_ws = sweep_dimtree_ws(c, X->dims, R, prec);
   const float* cf[3] = {factors[0], factors[1], factors[2]};
@@ -422,7 +479,7 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
     if (R <= mtk::kJobMaxRank) {
       const mtk::FactorArgs f = mtk::factor_args(X->dims, R, n, maxdim, solve_ws, c->d_status);
       mtk::MSlices ms;
-      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st, &ms, &f);
+      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, cws, dt_ws, st, &ms, &f);
       if (s != MTK_OK) return s;
       hipError_t e = mtk::launch_apply(X->dims, R, n, ms, factors[n], lambda, maxdim, solve_ws, c->d_status, st,
                                        n == 2);
@@ -431,7 +488,7 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
     }
     if (!overlap) {
       mtk::MSlices ms;
-      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st, &ms);
+      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, cws, dt_ws, st, &ms);
       if (s != MTK_OK) return s;
       hipError_t e = mtk::launch_update(X->dims, R, n, ms, factors[n], lambda, maxdim, solve_ws, c->d_status, st,
                                         n == 2);
@@ -444,14 +501,14 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
     if (e != hipSuccess) return hip_fail(c, e, "factorisation launch");
     HIP_OR_FAIL(c, hipEventRecord(c->join_ev[n], c->side));
     mtk::MSlices ms;
-    mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, scratch, dt_ws, st, &ms);
+    mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, cws, dt_ws, st, &ms);
     if (s != MTK_OK) return s;
     HIP_OR_FAIL(c, hipStreamWaitEvent(st, c->join_ev[n], 0));
     e = mtk::launch_apply(X->dims, R, n, ms, factors[n], lambda, maxdim, solve_ws, c->d_status, st, n == 2);
     if (e != hipSuccess) return hip_fail(c, e, "update launch");
   }
   if (with_fit) {
-    hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, R, c->d_fit, scratch, st);
+    hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, R, c->d_fit, cws, st);
     if (e != hipSuccess) return hip_fail(c, e, "fit launch");
   }
   return MTK_OK;
@@ -548,13 +605,13 @@ mtk_status als_run(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], dou
   const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
   const size_t need = round256((size_t)maxdim * R * sizeof(float)) + sweep_scratch_bytes(X->dims, (int)R, prec);
   if ((s = ensure_ws(c, need, st)) != MTK_OK) return s;
-  void* scratch = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
+  void* cws = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
   const float* cf[3] = {factors[0], factors[1], factors[2]};
   if (max_sweeps > 0) {
     hipGraphExec_t exec = nullptr;
     if ((s = sweep_graph(c, X, factors, lambda, (int)R, prec, false, &exec)) != MTK_OK) return s;
     double acc[2] = {0.0, 0.0};
-    hipError_t e = mtk::launch_sumsq(X->data, X->fmt, X->slice_exp, X->dims, c->d_fit, scratch, st);
+    hipError_t e = mtk::launch_sumsq(X->data, X->fmt, X->slice_exp, X->dims, c->d_fit, cws, st);
     if (e != hipSuccess) return hip_fail(c, e, "norm launch");
     HIP_OR_FAIL(c, hipMemcpyAsync(acc, c->d_fit, sizeof(acc), hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(c, hipStreamSynchronize(st));   // acc is host memory written by the copy
@@ -580,7 +637,7 @@ mtk_status als_run(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], dou
   }
   if (fit_final) {
     double acc[2] = {0.0, 0.0};
-    hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, (int)R, c->d_fit, scratch, st);
+    hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, (int)R, c->d_fit, cws, st);
     if (e != hipSuccess) return hip_fail(c, e, "fit launch");
     HIP_OR_FAIL(c, hipMemcpyAsync(acc, c->d_fit, sizeof(acc), hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(c, hipStreamSynchronize(st));

@@ -163,6 +163,7 @@ struct mtk_ctx {
   double* d_fit = nullptr;        // fit accumulators
   std::string last_error;
   std::vector<void*> retired_ws;  // outgrown workspace blocks (freed by mtk_graph_reset / mtk_destroy)
+  void* scratch = nullptr;        // device address of mttkrp_noalloc's static scratch on this device
   void* graph_cache = nullptr;    // als_sweep graph cache (see api.hip)
   hipStream_t side = nullptr;     // second stream of the captured sweep (factorisation)
   hipEvent_t fork_ev[3] = {nullptr, nullptr, nullptr};

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "MTK_OK", -1: "MTK_EINVAL", -2: "MTK_ENOMEM", -3: "MTK_EHIP",
                 -5: "MTK_EUNSUPPORTED", -6: "MTK_EBUDGET", -7: "MTK_EAGAIN"}
 
 EXPORTED = ["mtk_create", "mtk_destroy", "mtk_last_error", "mtk_check", "mtk_reserve",
-            "mtk_quantize_fp8", "mttkrp", "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
+            "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
             "als_sweep", "als_run", "mtk_graph_reset",
             "mtk_server_create", "mtk_server_submit", "mtk_server_poll", "mtk_server_stats",
             "mtk_server_destroy"]
@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
         "mtk_reserve": (i32, [vp, ctypes.POINTER(i64), i64, i32]),
         "mtk_quantize_fp8": (i32, [vp, vp, ctypes.POINTER(i64), vp, vp, vp, vp]),
         "mttkrp": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
+        "mttkrp_noalloc": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mttkrp_dimtree": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mtk_sweep_uses_dimtree": (i32, [ctypes.POINTER(i64), i64, i32]),
         "gram_solve": (i32, [vp, P3, ctypes.POINTER(i64), i64, i32, vp, vp, vp, vp]),
@@ -195,6 +196,17 @@ class Context:
         fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
         self._chk(self._L.mttkrp(self.h, ctypes.byref(d), fp, R, int(mode), _prec(prec), _ptr(out),
                                  _stream(stream)))
+        return out
+
+    def mttkrp_noalloc(self, X, factors, mode: int, out, prec="fp32", slice_exp=None, R=None, stream=None,
+                       X_t=None):
+        """mttkrp into a caller-provided ``out`` with no device allocation (the
+        library's static scratch; calls on one device must not overlap)."""
+        R = int(R if R is not None else next(f for f in factors if f is not None).shape[1])
+        d = self.tensor_desc(X, slice_exp, X_t=X_t)
+        fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
+        self._chk(self._L.mttkrp_noalloc(self.h, ctypes.byref(d), fp, R, int(mode), _prec(prec), _ptr(out),
+                                         _stream(stream)))
         return out
 
     def mttkrp_dimtree(self, X, factors, mode: int, prec="fp32", out=None, R=None, stream=None):
