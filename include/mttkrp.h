@@ -246,11 +246,18 @@ mtk_status mtk_graph_reset(mtk_ctx* ctx);
  *
  * A server owns a device, an HBM budget and a worker thread.  Requests
  * (a host FP32 tensor, rank R, sweep count) are admitted in arrival order
- * when their device bytes (tensor + factors + workspace) fit in the budget
- * next to the requests already resident; each admitted request gets its
- * own stream, so the sweeps of all resident requests overlap on the GPU.
- * A request's result depends only on its own inputs (same kernels and
- * summation order as a lone als_sweep call), never on what runs beside it.
+ * when a slot is free and their device block fits in the server's device
+ * arena, whose footprint (device bytes actually allocated) never exceeds the
+ * budget.  Every admitted request advances by one mode update per scheduler
+ * step, and a step is one replay of a HIP graph captured when the server is
+ * created: a grouped contraction over the tiles of all resident requests
+ * (each at its own mode, shape and rank), a grouped inversion of their
+ * normal-equation matrices, a grouped solve and a grouped normalisation,
+ * driven by a device table with one entry per request.  Factor state stays
+ * on the device until the request completes.  A request's result depends
+ * only on its own inputs (its plan and summation orders are fixed by its
+ * shape, rank, mode and precision), so it is bitwise the same alone and in
+ * any mix.
  * --------------------------------------------------------------------- */
 typedef struct mtk_server mtk_server;
 
@@ -265,8 +272,9 @@ typedef struct {
   double t_done;           /* result copied back to host */
 } mtk_result;
 
-/* budget_bytes: device bytes the server may hold for resident requests.
- * max_slots: most requests resident at once (>= 1). */
+/* budget_bytes: device bytes the server may hold for resident requests
+ * (the arena grows in chunks of min(1 GiB, budget) and never past it).
+ * max_slots: most requests resident at once (1 .. 64). */
 mtk_status mtk_server_create(mtk_server** srv, int device, uint64_t budget_bytes,
                              int max_slots);
 
@@ -280,13 +288,26 @@ mtk_status mtk_server_submit(mtk_server* srv, int64_t id, const float* x, const 
                              int64_t R, int prec, int sweeps, const float* const init[3],
                              float* const factors_out[3], double* lambda_out);
 
+/* Device bytes a request of this shape, rank and precision (MTK_FP32 or
+ * MTK_BF16X3) takes while resident: tensor, factors, lambda, partial sums,
+ * solve and fit scratch.  0 for an invalid request.  Host-only. */
+uint64_t mtk_server_request_bytes(const int64_t dims[3], int64_t R, int prec);
+
 /* Retrieve up to `cap` finished requests (oldest first).  Waits up to
  * timeout_s seconds for at least one; returns the count in *n. */
 mtk_status mtk_server_poll(mtk_server* srv, mtk_result* out, int cap, int* n, double timeout_s);
 
-/* Stats: resident requests, bytes in use, peak bytes in use. */
-mtk_status mtk_server_stats(mtk_server* srv, int* resident, uint64_t* bytes_in_use,
-                            uint64_t* peak_bytes);
+typedef struct {
+  int32_t resident;             /* requests admitted and not yet returned */
+  int32_t max_batch;            /* most requests carried by one step */
+  uint64_t bytes_in_use;        /* device bytes of the resident requests' blocks */
+  uint64_t peak_bytes_in_use;   /* largest bytes_in_use so far */
+  uint64_t device_bytes;        /* device memory the arena holds (<= budget) */
+  uint64_t steps;               /* scheduler steps launched */
+} mtk_server_stat;
+
+/* Counters of the server (a snapshot). */
+mtk_status mtk_server_stats(mtk_server* srv, mtk_server_stat* out);
 
 /* Finish every submitted request, then stop the worker and free the device
  * memory.  NULL is a no-op. */

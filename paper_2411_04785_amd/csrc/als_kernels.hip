@@ -17,6 +17,7 @@
 // Every reduction runs in a fixed order, so the update is deterministic.
 
 #include "mtk_internal.h"
+#include "srv_internal.h"
 #include "factor_device.h"
 
 #include <algorithm>
@@ -127,17 +128,18 @@ __global__ __launch_bounds__(256) void gj_inv_kernel(FactorArgs f) {
 // k mod 8 in increasing k, then the 8 partials in order), so an update can
 // take them without a separate reduction; S = 1 is a plain M.  Also writes
 // the row block's sums of F^2 per column (rows in a fixed order).
-__global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M, int S, int64_t sstride, int64_t n,
-                                                    int R, const double* __restrict__ Vinv,
-                                                    const int* __restrict__ status, double* __restrict__ F,
-                                                    double* __restrict__ colsq, double* __restrict__ ipsum) {
+// Workgroup (bx, by) of the apply launch (grid nblk x ceil(R/16)).
+__device__ __forceinline__ void apply_body(const float* __restrict__ M, int S, int64_t sstride, int64_t n, int R,
+                                           const double* __restrict__ Vinv, const int* __restrict__ status,
+                                           double* __restrict__ F, double* __restrict__ colsq,
+                                           double* __restrict__ ipsum, int64_t bx, int by) {
   if (*status & kStatusNotSPD) return;
   __shared__ double Vs[kMaxRank * 16];
   __shared__ float Ms[kApplyRows][kMaxRank + 1];
   __shared__ double red[16][16];
   const int tid = threadIdx.x, c = tid & 15, g = tid >> 4;
-  const int cb = blockIdx.y * 16;
-  const int64_t q0 = (int64_t)blockIdx.x * kApplyRows;
+  const int cb = by * 16;
+  const int64_t q0 = bx * kApplyRows;
   // Staging loads use clamped in-range indices and go out in batches before
   // any is stored.
   {
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
     double t = 0.0;
 #pragma unroll
     for (int gg = 0; gg < 16; ++gg) t += red[gg][tid];
-    colsq[(int64_t)blockIdx.x * R + cb + tid] = t;
+    colsq[bx * R + cb + tid] = t;
   }
   if (ipsum) {                       // <F, M> of this block, per column (same order as colsq)
     __syncthreads();
@@ -219,9 +221,16 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
       double t = 0.0;
 #pragma unroll
       for (int gg = 0; gg < 16; ++gg) t += red[gg][tid];
-      ipsum[(int64_t)blockIdx.x * R + cb + tid] = t;
+      ipsum[bx * R + cb + tid] = t;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M, int S, int64_t sstride, int64_t n,
+                                                    int R, const double* __restrict__ Vinv,
+                                                    const int* __restrict__ status, double* __restrict__ F,
+                                                    double* __restrict__ colsq, double* __restrict__ ipsum) {
+  apply_body(M, S, sstride, n, R, Vinv, status, F, colsq, ipsum, blockIdx.x, blockIdx.y);
 }
 
 // lambda_c = sqrt(sum over row blocks of colsq) (fixed order, recomputed by
@@ -229,19 +238,21 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
 // and the Gram partials of that FP32 factor.  Grid (tile pairs, row blocks);
 // the workgroups of diagonal tiles write the factor's columns of their tile,
 // and those of row block 0 write lambda.
-__global__ __launch_bounds__(256) void normalize_gram_kernel(const double* __restrict__ F, int64_t n, int R,
-                                                             const double* __restrict__ colsq, int nblk,
-                                                             const int* __restrict__ status, double* __restrict__ lam,
-                                                             float* __restrict__ out, double* __restrict__ part,
-                                                             const double* __restrict__ ipsum, double* __restrict__ ip) {
+// Workgroup (bx = tile pair, by = row block) of the normalise launch.
+__device__ __forceinline__ void normalize_gram_body(const double* __restrict__ F, int64_t n, int R,
+                                                    const double* __restrict__ colsq, int nblk,
+                                                    const int* __restrict__ status, double* __restrict__ lam,
+                                                    float* __restrict__ out, double* __restrict__ part,
+                                                    const double* __restrict__ ipsum, double* __restrict__ ip,
+                                                    int bx, int by) {
   if (*status & kStatusNotSPD) return;
   __shared__ double lsum[8][32];
   __shared__ double lt[32];
   __shared__ double ired[256];
   int tr, ts;
-  tile_pair(blockIdx.x, tr, ts);
+  tile_pair(bx, tr, ts);
   const int tid = threadIdx.x;
-  if (ipsum && blockIdx.x == 0 && blockIdx.y == 0) {
+  if (ipsum && bx == 0 && by == 0) {
     // <F, M> over the whole factor: strided per-thread sums, then a tree, in
     // fixed order.
     const int64_t ne = (int64_t)nblk * R;
@@ -287,10 +298,10 @@ __global__ __launch_bounds__(256) void normalize_gram_kernel(const double* __res
     for (int q = 0; q < 8; ++q) t += lsum[q][tid];
     lt[tid] = sqrt(t);
     const int col = (tid < 16 ? tr : ts) * 16 + (tid & 15);
-    if (diag && tid < 16 && blockIdx.y == 0 && col < R) lam[col] = lt[tid];
+    if (diag && tid < 16 && by == 0 && col < R) lam[col] = lt[tid];
   }
   __syncthreads();
-  const int rb = blockIdx.y;
+  const int rb = by;
   const int64_t rows = gram_rows(n, R);
   const int64_t i0 = (int64_t)rb * rows, i1 = min(n, i0 + rows);
   auto load = [&](int64_t i, int col) { return F[i * R + col]; };
@@ -302,7 +313,70 @@ __global__ __launch_bounds__(256) void normalize_gram_kernel(const double* __res
     if (diag) out[i * R + col] = v;
   };
   const double acc = gram_tile_rows(i0, i1, R, tr, ts, load, conv, emit);
-  gram_store(acc, part, blockIdx.x, rb);
+  gram_store(acc, part, bx, rb);
+}
+
+__global__ __launch_bounds__(256) void normalize_gram_kernel(const double* __restrict__ F, int64_t n, int R,
+                                                             const double* __restrict__ colsq, int nblk,
+                                                             const int* __restrict__ status, double* __restrict__ lam,
+                                                             float* __restrict__ out, double* __restrict__ part,
+                                                             const double* __restrict__ ipsum, double* __restrict__ ip) {
+  normalize_gram_body(F, n, R, colsq, nblk, status, lam, out, part, ipsum, ip, blockIdx.x, blockIdx.y);
+}
+
+}  // namespace
+
+namespace {
+
+// Grouped update kernels of a serving step (see srv_internal.h).  Each
+// workgroup strides over the step's work items, finds its request and runs
+// the same body as the single-request launch; the barrier at the end of an
+// item keeps the next item's LDS writes behind this item's reads.
+
+// V^{-1} of every request: one workgroup per entry.
+__global__ __launch_bounds__(256) void srv_factor_kernel(const SrvTable* __restrict__ t) {
+  extern __shared__ double flds[];
+  for (int q = blockIdx.x; q < t->nreq; q += gridDim.x) {
+    const FactorArgs f = t->e[q].u.fa;
+    switch ((f.R + 15) / 16) {
+      case 1: factor_gj<1>(f, flds); break;
+      case 2: factor_gj<2>(f, flds); break;
+      case 3: factor_gj<3>(f, flds); break;
+      case 4: factor_gj<4>(f, flds); break;
+      case 5: factor_gj<5>(f, flds); break;
+      case 6: factor_gj<6>(f, flds); break;
+      case 7: factor_gj<7>(f, flds); break;
+      default: factor_gj<8>(f, flds); break;
+    }
+    __syncthreads();
+  }
+}
+
+// F = M V^{-1} of every request: workgroup (row block, column block).
+__global__ __launch_bounds__(256) void srv_apply_kernel(const SrvTable* __restrict__ t) {
+  const int nreq = t->nreq;
+  for (int64_t w = blockIdx.x; w < t->n_ab; w += gridDim.x) {
+    const int q = srv_find(nreq, w, [&](int i) { return t->e[i].ab0; });
+    const SrvUpdate& u = t->e[q].u;
+    const int64_t local = w - t->e[q].ab0;
+    apply_body(u.M, u.S, u.sstride, u.n, u.R, u.fa.vinv, u.status, u.F, u.colsq, nullptr, local % u.nblk,
+               (int)(local / u.nblk));
+    __syncthreads();
+  }
+}
+
+// lambda, the normalised factor and its Gram partials: workgroup (tile pair, row block).
+__global__ __launch_bounds__(256) void srv_normalize_kernel(const SrvTable* __restrict__ t) {
+  const int nreq = t->nreq;
+  for (int64_t w = blockIdx.x; w < t->n_nb; w += gridDim.x) {
+    const int q = srv_find(nreq, w, [&](int i) { return t->e[i].nb0; });
+    const SrvUpdate& u = t->e[q].u;
+    const int64_t local = w - t->e[q].nb0;
+    const int np = gram_pairs(u.R);
+    normalize_gram_body(u.F, u.n, u.R, u.colsq, u.nblk, u.status, u.lam, u.fout, u.gram_out, nullptr, nullptr,
+                        (int)(local % np), (int)(local / np));
+    __syncthreads();
+  }
 }
 
 }  // namespace
@@ -576,6 +650,47 @@ __global__ __launch_bounds__(256) void fit_final_kernel(const double* __restrict
 }
 
 }  // namespace
+
+SrvUpdate srv_update(const int64_t dims[3], int R, int mode, int64_t maxdim, void* solve_ws_p, const float* M,
+                     int S, int64_t sstride, float* fout, double* lam, int* status) {
+  SolveWs w = solve_ws(maxdim, R, solve_ws_p);
+  SrvUpdate u{};
+  u.fa = factor_args(dims, R, mode, maxdim, solve_ws_p, status);
+  u.M = M;
+  u.S = S;
+  u.sstride = sstride;
+  u.n = dims[mode];
+  u.R = R;
+  u.nblk = (int)cdiv(u.n, kApplyRows);
+  u.nrb = gram_blocks(u.n, R);
+  u.F = w.F;
+  u.colsq = w.colsq;
+  u.lam = lam;
+  u.fout = fout;
+  u.gram_out = w.part[mode];
+  u.status = status;
+  return u;
+}
+
+int64_t srv_apply_blocks(const SrvUpdate& u) { return (int64_t)u.nblk * ((u.R + 15) / 16); }
+int64_t srv_normalize_blocks(const SrvUpdate& u) { return (int64_t)gram_pairs(u.R) * u.nrb; }
+
+size_t srv_factor_lds_bytes(int max_rank) { return factor_gj_lds_bytes(max_rank); }
+
+hipError_t launch_srv_factor(const SrvTable* t, int max_rank, hipStream_t st) {
+  hipLaunchKernelGGL(srv_factor_kernel, dim3(kSrvMaxReq), dim3(256), srv_factor_lds_bytes(max_rank), st, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_srv_apply(const SrvTable* t, hipStream_t st) {
+  hipLaunchKernelGGL(srv_apply_kernel, dim3(kSrvApplyGrid), dim3(256), 0, st, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_srv_normalize(const SrvTable* t, hipStream_t st) {
+  hipLaunchKernelGGL(srv_normalize_kernel, dim3(kSrvNormalizeGrid), dim3(256), 0, st, t);
+  return hipGetLastError();
+}
 
 size_t fit_ws_bytes(const int64_t dims[3]) {
   return (size_t)dims[0] * cdiv(dims[1], 16) * 2 * sizeof(double) + 256;

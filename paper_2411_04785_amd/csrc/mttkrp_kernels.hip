@@ -29,6 +29,7 @@
 // (dims, R, mode, precision) alone, so results are bitwise reproducible.
 
 #include "mtk_internal.h"
+#include "srv_internal.h"
 #include "factor_device.h"
 #include "fp8_codec.h"
 #include "tile_device.h"
@@ -52,6 +53,7 @@ struct KArgs {
   int nM, nRed, nLoop, R;
   int wr, mt_per_wg, n_rg, n_mg, loop_block, n_lb;
   int ncg;                    // column groups: waves splitting R over the same tile
+  int cb0;                    // first column of the workgroup (grouped launches: column tile * 16)
   int mode;
   int job_on;                 // 1: workgroup 0 inverts job's V, the rest shift by one
   FactorArgs job;
@@ -165,12 +167,11 @@ __device__ __forceinline__ void load_frag(Frag<PREC, NT, NV>& fr, const KArgs& a
   }
 }
 
-template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
-__global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
-  extern __shared__ float dyn_lds[];
-  if constexpr (NT <= 2) {
-    if (run_job(a, dyn_lds)) return;
-  }
+// One workgroup's share of a contraction launch: workgroup `bid` of the
+// plan in `a` (dyn_lds: the launch's dynamic LDS).  The waves that added
+// their partial tiles into another wave's return early.
+template <int PREC, int NT, int NV, bool CONTIG, bool VEC, bool GROUPED = false>
+__device__ __forceinline__ void contract_body(const KArgs& a, int bid, float* dyn_lds) {
   constexpr int KW = 4 * NV;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -179,7 +180,6 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
 
   // Workgroup -> (reduction group, M group, loop block); the reduction group
   // varies fastest so neighbouring workgroups read neighbouring windows.
-  int bid = (int)blockIdx.x - a.job_on;
   const int rg = bid % a.n_rg; bid /= a.n_rg;
   const int mg = bid % a.n_mg; bid /= a.n_mg;
   const int lb = bid;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
   const int cg = wave % a.ncg;
   const int wred = (wave / a.ncg) % a.wr;
   const int wm = wave / (a.ncg * a.wr);
-  const int cb = cg * NT * 16;                        // first column of this wave
+  const int cb = (GROUPED ? a.cb0 : 0) + cg * NT * 16;   // first column of this wave
   const int win = rg * a.wr + wred;                   // reduction window of this wave
   const int red_base = win * KW;
   // This lane's first reduction value (FP8: its first 16-byte piece).
@@ -313,6 +313,15 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
       if (orow < a.nM) outp[(int64_t)orow * a.R + col] = acc[t][v];
     }
   }
+}
+
+template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
+__global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
+  extern __shared__ float dyn_lds[];
+  if constexpr (NT <= 2) {
+    if (run_job(a, dyn_lds)) return;
+  }
+  contract_body<PREC, NT, NV, CONTIG, VEC>(a, (int)blockIdx.x - a.job_on, dyn_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -511,12 +520,12 @@ __global__ __launch_bounds__(256) void contract_cm_kernel(KArgs a) {
 // consecutive elements with 8 slice groups: group q sums slices q, q+8, ...
 // in increasing order, then the 8 group sums are added in group order.  The
 // order depends only on S, so the result is deterministic.
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int S,
-                                                            int64_t n, float* __restrict__ out) {
+__device__ __forceinline__ void splitk_reduce_body(const float* __restrict__ part, int S, int64_t n,
+                                                   float* __restrict__ out, int64_t blk) {
   __shared__ float red[8][33];
   const int eo = threadIdx.x & 31;
   const int q = threadIdx.x >> 5;
-  const int64_t e = (int64_t)blockIdx.x * 32 + eo;
+  const int64_t e = blk * 32 + eo;
   // Slices q, q + 8, ... in order; their loads go out 8 at a time (clamped
   // to the last slice) ahead of the adds.
   float s = 0.f;
@@ -538,6 +547,11 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restr
     for (int k = 1; k < 8; ++k) t += red[k][eo];
     out[e] = t;
   }
+}
+
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ part, int S,
+                                                            int64_t n, float* __restrict__ out) {
+  splitk_reduce_body(part, S, n, out, blockIdx.x);
 }
 
 __device__ __forceinline__ float e4m3_decode_dev(uint32_t c) {
@@ -613,6 +627,46 @@ __global__ __launch_bounds__(256) void frag_quant_kernel(const float* __restrict
   if (threadIdx.x == 0) {
     ex[r] = eh;
     ex[R + r] = el;
+  }
+}
+
+// Grouped contraction of a serving step: work item w belongs to the entry
+// whose first item is the largest one <= w; its local index splits into the
+// 16-column tile (fastest) and the workgroup of that request's plan.  A
+// request's items compute exactly what its own launch would, so the
+// result does not depend on the other entries.  The barrier at the end of
+// an item keeps the next item's LDS staging behind this item's reads.
+__global__ __launch_bounds__(256) void srv_contract_kernel(const SrvTable* __restrict__ t) {
+  extern __shared__ float dyn_lds[];
+  const int nreq = t->nreq;
+  const int64_t nwi = t->n_wi;
+  for (int64_t w = blockIdx.x; w < nwi; w += gridDim.x) {
+    const int q = srv_find(nreq, w, [&](int i) { return t->e[i].wi0; });
+    const SrvContract& c = t->e[q].c;
+    int local = (int)(w - t->e[q].wi0);
+    const int ct = local % c.nct;
+    local /= c.nct;
+    KArgs a{};
+    a.X = c.X;
+    a.frag_src = c.frag;
+    a.weight = c.weight;
+    a.part = c.part;
+    a.sM = c.sM; a.sRed = c.sRed; a.sLoop = c.sLoop;
+    a.nM = c.nM; a.nRed = c.nRed; a.nLoop = c.nLoop; a.R = c.R;
+    a.wr = c.wr; a.mt_per_wg = c.mt_per_wg; a.n_rg = c.n_rg; a.n_mg = c.n_mg;
+    a.loop_block = c.loop_block; a.n_lb = c.n_lb;
+    a.ncg = 1;
+    a.cb0 = ct * 16;
+    a.mode = c.mode;
+    switch (c.prec * 3 + c.form) {
+      case 0: contract_body<MTK_FP32, 1, 8, true, true, true>(a, local, dyn_lds); break;
+      case 1: contract_body<MTK_FP32, 1, 8, true, false, true>(a, local, dyn_lds); break;
+      case 2: contract_body<MTK_FP32, 1, 8, false, false, true>(a, local, dyn_lds); break;
+      case 3: contract_body<MTK_BF16X3, 1, 8, true, true, true>(a, local, dyn_lds); break;
+      case 4: contract_body<MTK_BF16X3, 1, 8, true, false, true>(a, local, dyn_lds); break;
+      default: contract_body<MTK_BF16X3, 1, 8, false, false, true>(a, local, dyn_lds); break;
+    }
+    __syncthreads();
   }
 }
 
@@ -869,6 +923,57 @@ hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void
 
 hipError_t launch_slice_reduce(const float* part, int slices, int64_t n, float* out, hipStream_t st) {
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(n, 32)), dim3(256), 0, st, part, slices, n, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Serving: plan of one request's contraction in a grouped step.  nv = 8
+// (kw = 32 values per wave window), one 16-column tile per workgroup; modes
+// 0 and 1 reduce over contiguous k (up to 4 waves on adjacent windows),
+// mode 2 over strided j (4 waves on adjacent 16-row tiles).  The outer loop
+// is split so that a workgroup covers about 32K tensor elements, with at
+// most 128 partial slices.  Everything depends on (dims, R, mode, prec)
+// only.
+// ---------------------------------------------------------------------------
+SrvContract srv_contract_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16) {
+  SrvContract c{};
+  const int64_t I = dims[0], J = dims[1], K = dims[2];
+  c.R = R;
+  c.mode = mode;
+  c.prec = prec;
+  if (mode == 0) { c.nM = (int)I; c.nRed = (int)K; c.nLoop = (int)J; c.sM = J * K; c.sRed = 1; c.sLoop = K; }
+  else if (mode == 1) { c.nM = (int)J; c.nRed = (int)K; c.nLoop = (int)I; c.sM = K; c.sRed = 1; c.sLoop = J * K; }
+  else { c.nM = (int)K; c.nRed = (int)J; c.nLoop = (int)I; c.sM = 1; c.sRed = K; c.sLoop = J * K; }
+  constexpr int kw = 32;
+  if (mode != 2) {
+    c.form = (x_aligned16 && c.nRed % 4 == 0) ? 0 : 1;
+    const int64_t windows = cdiv(c.nRed, kw);
+    c.wr = windows >= 4 ? 4 : (windows >= 2 ? 2 : 1);
+  } else {
+    c.form = 2;
+    c.wr = 1;
+  }
+  c.mt_per_wg = 4 / c.wr;
+  c.n_rg = (int)cdiv(c.nRed, (int64_t)c.wr * kw);
+  c.n_mg = (int)cdiv(cdiv(c.nM, 16), c.mt_per_wg);
+  c.nct = (int)cdiv(R, 16);
+  const int64_t base = (int64_t)c.n_rg * c.n_mg * c.nct;
+  const int64_t want = std::max<int64_t>(1, cdiv(I * J * K, 32768));
+  int64_t n_lb = std::max<int64_t>(1, std::min<int64_t>(c.nLoop, cdiv(want, base)));
+  while (n_lb > 1 && (int64_t)c.n_rg * n_lb > 128) n_lb = cdiv(n_lb, 2);
+  c.loop_block = (int)cdiv(c.nLoop, n_lb);
+  c.loop_block = std::min(c.loop_block, std::max(1, MTK_STAGE_FLOATS / R));
+  c.n_lb = (int)cdiv(c.nLoop, c.loop_block);
+  c.slices = c.n_rg * c.n_lb;
+  return c;
+}
+
+int64_t srv_contract_items(const SrvContract& c) { return (int64_t)c.n_rg * c.n_mg * c.n_lb * c.nct; }
+
+size_t srv_contract_lds_bytes() { return ((size_t)MTK_STAGE_FLOATS + 4 * 4 * 64) * sizeof(float); }
+
+hipError_t launch_srv_contract(const SrvTable* t, hipStream_t st) {
+  hipLaunchKernelGGL(srv_contract_kernel, dim3(kSrvContractGrid), dim3(256), srv_contract_lds_bytes(), st, t);
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ EXPORTED = ["mtk_create", "mtk_destroy", "mtk_last_error", "mtk_check", "mtk_res
             "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
             "als_sweep", "als_run", "mtk_graph_reset",
             "mtk_server_create", "mtk_server_submit", "mtk_server_poll", "mtk_server_stats",
-            "mtk_server_destroy"]
+            "mtk_server_request_bytes", "mtk_server_destroy"]
 
 
 class MtkError(RuntimeError):
@@ -45,6 +45,12 @@ class NotSPDError(MtkError):
 class Tensor(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("data_t", ctypes.c_void_p), ("dims", ctypes.c_int64 * 3),
                 ("fmt", ctypes.c_int32), ("slice_exp", ctypes.c_void_p)]
+
+
+class ServerStat(ctypes.Structure):
+    _fields_ = [("resident", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("bytes_in_use", ctypes.c_uint64),
+                ("peak_bytes_in_use", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64)]
 
 
 class Result(ctypes.Structure):
@@ -86,8 +92,8 @@ def lib() -> ctypes.CDLL:
         "mtk_server_create": (i32, [ctypes.POINTER(vp), i32, ctypes.c_uint64, i32]),
         "mtk_server_submit": (i32, [vp, i64, vp, ctypes.POINTER(i64), i64, i32, i32, P3, P3, vp]),
         "mtk_server_poll": (i32, [vp, ctypes.POINTER(Result), i32, ctypes.POINTER(i32), d]),
-        "mtk_server_stats": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_uint64),
-                                   ctypes.POINTER(ctypes.c_uint64)]),
+        "mtk_server_stats": (i32, [vp, ctypes.POINTER(ServerStat)]),
+        "mtk_server_request_bytes": (ctypes.c_uint64, [ctypes.POINTER(i64), i64, i32]),
         "mtk_server_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -278,7 +284,9 @@ class Context:
 
 
 class Server:
-    """mtk_server: continuous batching of CP-ALS decompositions on one device.
+    """mtk_server: continuous batching of CP-ALS decompositions on one device
+    (every resident request advances one mode update per scheduler step; a
+    step is a captured graph of grouped launches over all of them).
 
     submit() copies the host inputs; results land in host arrays owned by
     this object until poll() returns them."""
@@ -291,6 +299,11 @@ class Server:
             raise MtkError(st, "mtk_server_create failed")
         self.h = h
         self._live = {}
+
+    @staticmethod
+    def request_bytes(dims, R: int, prec="fp32") -> int:
+        """Device bytes a request takes while resident (0 if invalid)."""
+        return int(lib().mtk_server_request_bytes(_dims(dims), int(R), _prec(prec)))
 
     def submit(self, rid: int, X: np.ndarray, init: Sequence[np.ndarray], prec="fp32", sweeps: int = 10):
         X = np.ascontiguousarray(X, dtype=np.float32)
@@ -323,9 +336,9 @@ class Server:
         return res
 
     def stats(self):
-        res, used, peak = ctypes.c_int(), ctypes.c_uint64(), ctypes.c_uint64()
-        self._L.mtk_server_stats(self.h, ctypes.byref(res), ctypes.byref(used), ctypes.byref(peak))
-        return {"resident": res.value, "bytes_in_use": used.value, "peak_bytes": peak.value}
+        st = ServerStat()
+        self._L.mtk_server_stats(self.h, ctypes.byref(st))
+        return {k: getattr(st, k) for k, _ in ServerStat._fields_}
 
     def close(self):
         if getattr(self, "h", None):
