@@ -334,10 +334,10 @@ namespace {
 // item keeps the next item's LDS writes behind this item's reads.
 
 // V^{-1} of every request: one workgroup per entry.
-__global__ __launch_bounds__(256) void srv_factor_kernel(const SrvTable* __restrict__ t) {
+__global__ __launch_bounds__(256) void srv_factor_kernel(const SrvTable* __restrict__ t, int upd) {
   extern __shared__ double flds[];
   for (int q = blockIdx.x; q < t->nreq; q += gridDim.x) {
-    const FactorArgs f = t->e[q].u.fa;
+    const FactorArgs f = t->e[q][upd].u.fa;
     switch ((f.R + 15) / 16) {
       case 1: factor_gj<1>(f, flds); break;
       case 2: factor_gj<2>(f, flds); break;
@@ -353,12 +353,12 @@ __global__ __launch_bounds__(256) void srv_factor_kernel(const SrvTable* __restr
 }
 
 // F = M V^{-1} of every request: workgroup (row block, column block).
-__global__ __launch_bounds__(256) void srv_apply_kernel(const SrvTable* __restrict__ t) {
+__global__ __launch_bounds__(256) void srv_apply_kernel(const SrvTable* __restrict__ t, int upd) {
   const int nreq = t->nreq;
-  for (int64_t w = blockIdx.x; w < t->n_ab; w += gridDim.x) {
-    const int q = srv_find(nreq, w, [&](int i) { return t->e[i].ab0; });
-    const SrvUpdate& u = t->e[q].u;
-    const int64_t local = w - t->e[q].ab0;
+  for (int64_t w = blockIdx.x; w < t->n_ab[upd]; w += gridDim.x) {
+    const int q = srv_find(nreq, w, [&](int i) { return t->e[i][upd].ab0; });
+    const SrvUpdate& u = t->e[q][upd].u;
+    const int64_t local = w - t->e[q][upd].ab0;
     apply_body(u.M, u.S, u.sstride, u.n, u.R, u.fa.vinv, u.status, u.F, u.colsq, nullptr, local % u.nblk,
                (int)(local / u.nblk));
     __syncthreads();
@@ -366,12 +366,12 @@ __global__ __launch_bounds__(256) void srv_apply_kernel(const SrvTable* __restri
 }
 
 // lambda, the normalised factor and its Gram partials: workgroup (tile pair, row block).
-__global__ __launch_bounds__(256) void srv_normalize_kernel(const SrvTable* __restrict__ t) {
+__global__ __launch_bounds__(256) void srv_normalize_kernel(const SrvTable* __restrict__ t, int upd) {
   const int nreq = t->nreq;
-  for (int64_t w = blockIdx.x; w < t->n_nb; w += gridDim.x) {
-    const int q = srv_find(nreq, w, [&](int i) { return t->e[i].nb0; });
-    const SrvUpdate& u = t->e[q].u;
-    const int64_t local = w - t->e[q].nb0;
+  for (int64_t w = blockIdx.x; w < t->n_nb[upd]; w += gridDim.x) {
+    const int q = srv_find(nreq, w, [&](int i) { return t->e[i][upd].nb0; });
+    const SrvUpdate& u = t->e[q][upd].u;
+    const int64_t local = w - t->e[q][upd].nb0;
     const int np = gram_pairs(u.R);
     normalize_gram_body(u.F, u.n, u.R, u.colsq, u.nblk, u.status, u.lam, u.fout, u.gram_out, nullptr, nullptr,
                         (int)(local % np), (int)(local / np));
@@ -677,18 +677,18 @@ int64_t srv_normalize_blocks(const SrvUpdate& u) { return (int64_t)gram_pairs(u.
 
 size_t srv_factor_lds_bytes(int max_rank) { return factor_gj_lds_bytes(max_rank); }
 
-hipError_t launch_srv_factor(const SrvTable* t, int max_rank, hipStream_t st) {
-  hipLaunchKernelGGL(srv_factor_kernel, dim3(kSrvMaxReq), dim3(256), srv_factor_lds_bytes(max_rank), st, t);
+hipError_t launch_srv_factor(const SrvTable* t, int u, int max_rank, hipStream_t st) {
+  hipLaunchKernelGGL(srv_factor_kernel, dim3(kSrvMaxReq), dim3(256), srv_factor_lds_bytes(max_rank), st, t, u);
   return hipGetLastError();
 }
 
-hipError_t launch_srv_apply(const SrvTable* t, hipStream_t st) {
-  hipLaunchKernelGGL(srv_apply_kernel, dim3(kSrvApplyGrid), dim3(256), 0, st, t);
+hipError_t launch_srv_apply(const SrvTable* t, int u, hipStream_t st) {
+  hipLaunchKernelGGL(srv_apply_kernel, dim3(kSrvApplyGrid), dim3(256), 0, st, t, u);
   return hipGetLastError();
 }
 
-hipError_t launch_srv_normalize(const SrvTable* t, hipStream_t st) {
-  hipLaunchKernelGGL(srv_normalize_kernel, dim3(kSrvNormalizeGrid), dim3(256), 0, st, t);
+hipError_t launch_srv_normalize(const SrvTable* t, int u, hipStream_t st) {
+  hipLaunchKernelGGL(srv_normalize_kernel, dim3(kSrvNormalizeGrid), dim3(256), 0, st, t, u);
   return hipGetLastError();
 }
 

@@ -636,14 +636,31 @@ __global__ __launch_bounds__(256) void frag_quant_kernel(const float* __restrict
 // request's items compute exactly what its own launch would, so the
 // result does not depend on the other entries.  The barrier at the end of
 // an item keeps the next item's LDS staging behind this item's reads.
-__global__ __launch_bounds__(256) void srv_contract_kernel(const SrvTable* __restrict__ t) {
+// With `with_factor`, the first nreq items each invert one request's V
+// (factor_gj, LDS within the launch's for R <= kSrvFusedMaxRank), so the
+// inversion overlaps the contraction with no launch of its own.
+__global__ __launch_bounds__(256) void srv_contract_kernel(const SrvTable* __restrict__ t, int upd, int with_factor) {
   extern __shared__ float dyn_lds[];
   const int nreq = t->nreq;
-  const int64_t nwi = t->n_wi;
+  const int64_t jobs = with_factor ? nreq : 0;
+  const int64_t nwi = t->n_wi[upd] + jobs;
   for (int64_t w = blockIdx.x; w < nwi; w += gridDim.x) {
-    const int q = srv_find(nreq, w, [&](int i) { return t->e[i].wi0; });
-    const SrvContract& c = t->e[q].c;
-    int local = (int)(w - t->e[q].wi0);
+    if (w < jobs) {
+      const FactorArgs f = t->e[w][upd].u.fa;
+      double* dl = reinterpret_cast<double*>(dyn_lds);
+      switch ((f.R + 15) / 16) {
+        case 1: factor_gj<1>(f, dl); break;
+        case 2: factor_gj<2>(f, dl); break;
+        case 3: factor_gj<3>(f, dl); break;
+        default: factor_gj<4>(f, dl); break;
+      }
+      __syncthreads();
+      continue;
+    }
+    const int64_t wc = w - jobs;
+    const int q = srv_find(nreq, wc, [&](int i) { return t->e[i][upd].wi0; });
+    const SrvContract& c = t->e[q][upd].c;
+    int local = (int)(wc - t->e[q][upd].wi0);
     const int ct = local % c.nct;
     local /= c.nct;
     KArgs a{};
@@ -970,10 +987,13 @@ SrvContract srv_contract_plan(const int64_t dims[3], int R, int mode, int prec, 
 
 int64_t srv_contract_items(const SrvContract& c) { return (int64_t)c.n_rg * c.n_mg * c.n_lb * c.nct; }
 
-size_t srv_contract_lds_bytes() { return ((size_t)MTK_STAGE_FLOATS + 4 * 4 * 64) * sizeof(float); }
+size_t srv_contract_lds_bytes() {
+  return std::max(((size_t)MTK_STAGE_FLOATS + 4 * 4 * 64) * sizeof(float), factor_gj_lds_bytes(kSrvFusedMaxRank));
+}
 
-hipError_t launch_srv_contract(const SrvTable* t, hipStream_t st) {
-  hipLaunchKernelGGL(srv_contract_kernel, dim3(kSrvContractGrid), dim3(256), srv_contract_lds_bytes(), st, t);
+hipError_t launch_srv_contract(const SrvTable* t, int u, bool with_factor, hipStream_t st) {
+  hipLaunchKernelGGL(srv_contract_kernel, dim3(kSrvContractGrid), dim3(256), srv_contract_lds_bytes(), st, t, u,
+                     with_factor ? 1 : 0);
   return hipGetLastError();
 }
 

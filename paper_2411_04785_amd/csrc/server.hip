@@ -6,13 +6,14 @@
 //    the arena's device footprint passing the HBM budget.  Admission queues
 //    the upload of the request's tensor and initial factors and the Gram
 //    matrices of its factors 1 and 2 on the copy stream;
-//  - steps: every uploaded request advances by one mode update per step.
-//    A step is one HIP graph, captured once when the server is created and
-//    replayed for every step: the grouped contraction of all resident
-//    requests (each at its own mode), the grouped inversion of their V on a
-//    parallel branch, then the grouped apply (F = M V^{-1}) and the grouped
-//    normalisation with the new factor's Gram partials (srv_internal.h).
-//    The host writes the step's request table (one entry per request) into
+//  - steps: every uploaded request advances by one CP-ALS sweep (three mode
+//    updates) per step.  A step is one HIP graph, captured when the server
+//    is created and replayed for every step: for each update, the grouped
+//    contraction of all resident requests with the grouped inversion of
+//    their V (inside the contraction launch when every rank is at most 64,
+//    else on a parallel branch), then the grouped apply (F = M V^{-1}) and
+//    the grouped normalisation with the new factor's Gram partials
+//    (srv_internal.h).  The host writes the step's request table into
 //    pinned memory and copies it to the device before each replay; two
 //    tables alternate, so the worker prepares a step while the previous one
 //    runs;
@@ -198,7 +199,7 @@ struct Req {
   Layout L{};
   mtk::SrvContract plan[3];
   int state = kPending;
-  int updates = 0;                 // mode updates queued so far
+  int done_sweeps = 0;             // sweeps queued so far
 };
 
 struct Slot {
@@ -223,8 +224,10 @@ struct mtk_server {
   // step that reads it, and the event that marks that step done.
   mtk::SrvTable* htab[2] = {nullptr, nullptr};
   mtk::SrvTable* dtab[2] = {nullptr, nullptr};
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // Captured steps per table and variant: [0] inversion inside the
+  // contraction launch (every R <= 64), [1] on a parallel branch (any R).
+  hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   hipEvent_t step_ev[2] = {nullptr, nullptr};
   bool step_pending[2] = {false, false};
   int next_tab = 0;
@@ -240,22 +243,30 @@ struct mtk_server {
   std::thread worker;
 
   hipError_t capture_steps() {
-    for (int b = 0; b < 2; ++b) {
-      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return e;
-      hipError_t le = hipEventRecord(fork_ev, cap);
-      if (le == hipSuccess) le = hipStreamWaitEvent(side, fork_ev, 0);
-      if (le == hipSuccess) le = mtk::launch_srv_factor(dtab[b], max_rank, side);
-      if (le == hipSuccess) le = mtk::launch_srv_contract(dtab[b], cap);
-      if (le == hipSuccess) le = hipEventRecord(join_ev, side);
-      if (le == hipSuccess) le = hipStreamWaitEvent(cap, join_ev, 0);
-      if (le == hipSuccess) le = mtk::launch_srv_apply(dtab[b], cap);
-      if (le == hipSuccess) le = mtk::launch_srv_normalize(dtab[b], cap);
-      e = hipStreamEndCapture(cap, &graph[b]);
-      if (le != hipSuccess) return le;
-      if (e != hipSuccess) return e;
-      if ((e = hipGraphInstantiate(&exec[b], graph[b], nullptr, nullptr, 0)) != hipSuccess) return e;
-    }
+    for (int b = 0; b < 2; ++b)
+      for (int v = 0; v < 2; ++v) {
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        hipError_t le = hipSuccess;
+        for (int u = 0; u < 3 && le == hipSuccess; ++u) {
+          if (v == 0) {
+            le = mtk::launch_srv_contract(dtab[b], u, true, cap);
+          } else {
+            le = hipEventRecord(fork_ev, cap);
+            if (le == hipSuccess) le = hipStreamWaitEvent(side, fork_ev, 0);
+            if (le == hipSuccess) le = mtk::launch_srv_factor(dtab[b], u, max_rank, side);
+            if (le == hipSuccess) le = mtk::launch_srv_contract(dtab[b], u, false, cap);
+            if (le == hipSuccess) le = hipEventRecord(join_ev, side);
+            if (le == hipSuccess) le = hipStreamWaitEvent(cap, join_ev, 0);
+          }
+          if (le == hipSuccess) le = mtk::launch_srv_apply(dtab[b], u, cap);
+          if (le == hipSuccess) le = mtk::launch_srv_normalize(dtab[b], u, cap);
+        }
+        e = hipStreamEndCapture(cap, &graph[b][v]);
+        if (le != hipSuccess) return le;
+        if (e != hipSuccess) return e;
+        if ((e = hipGraphInstantiate(&exec[b][v], graph[b][v], nullptr, nullptr, 0)) != hipSuccess) return e;
+      }
     return hipSuccess;
   }
 
@@ -294,9 +305,8 @@ struct mtk_server {
     return hipEventRecord(s.ready, copy);
   }
 
-  // The table entry of request r for its next update (mode r.updates % 3).
-  void fill_entry(Req& r, mtk::SrvEntry& en) {
-    const int n = r.updates % 3;
+  // The table entry of request r for update (mode) n of its next sweep.
+  void fill_entry(Req& r, int n, mtk::SrvEntry& en) {
     mtk::SrvContract c = r.plan[n];
     c.X = X(r);
     c.frag = n == 2 ? F(r, 1) : F(r, 2);
@@ -371,7 +381,7 @@ struct mtk_server {
     release(s);
   }
 
-  // One scheduler step over the running requests; false if none runs.
+  // One scheduler step (a sweep) over the running requests; false if none runs.
   bool step() {
     std::vector<Slot*> run;
     for (auto& s : slots)
@@ -385,22 +395,27 @@ struct mtk_server {
     }
     mtk::SrvTable* t = htab[b];
     t->nreq = (int)run.size();
-    int64_t wi = 0, ab = 0, nb = 0;
-    for (size_t q = 0; q < run.size(); ++q) {
-      mtk::SrvEntry& en = t->e[q];
-      fill_entry(*run[q]->req, en);
-      en.wi0 = wi;
-      en.ab0 = ab;
-      en.nb0 = nb;
-      wi += mtk::srv_contract_items(en.c);
-      ab += mtk::srv_apply_blocks(en.u);
-      nb += mtk::srv_normalize_blocks(en.u);
+    int rmax = 0;
+    for (int u = 0; u < 3; ++u) {
+      int64_t wi = 0, ab = 0, nb = 0;
+      for (size_t q = 0; q < run.size(); ++q) {
+        mtk::SrvEntry& en = t->e[q][u];
+        fill_entry(*run[q]->req, u, en);
+        en.wi0 = wi;
+        en.ab0 = ab;
+        en.nb0 = nb;
+        wi += mtk::srv_contract_items(en.c);
+        ab += mtk::srv_apply_blocks(en.u);
+        nb += mtk::srv_normalize_blocks(en.u);
+      }
+      t->n_wi[u] = wi;
+      t->n_ab[u] = ab;
+      t->n_nb[u] = nb;
     }
-    t->n_wi = wi;
-    t->n_ab = ab;
-    t->n_nb = nb;
+    for (Slot* s : run) rmax = std::max(rmax, s->req->R);
+    const int v = rmax <= mtk::kSrvFusedMaxRank ? 0 : 1;
     hipError_t e = hipMemcpyAsync(dtab[b], t, mtk::srv_table_bytes(t->nreq), hipMemcpyHostToDevice, compute);
-    if (e == hipSuccess) e = hipGraphLaunch(exec[b], compute);
+    if (e == hipSuccess) e = hipGraphLaunch(exec[b][v], compute);
     if (e == hipSuccess) e = hipEventRecord(step_ev[b], compute);
     if (e != hipSuccess) {
       for (Slot* s : run) fail_slot(*s, MTK_EHIP);
@@ -411,7 +426,7 @@ struct mtk_server {
     max_batch = std::max(max_batch, (int)run.size());
     for (Slot* s : run) {
       Req& r = *s->req;
-      if (++r.updates == 3 * r.sweeps && finish(*s) != hipSuccess) fail_slot(*s, MTK_EHIP);
+      if (++r.done_sweeps == r.sweeps && finish(*s) != hipSuccess) fail_slot(*s, MTK_EHIP);
     }
     return true;
   }
@@ -609,8 +624,10 @@ mtk_status mtk_server_destroy(mtk_server* s) {
   (void)hipSetDevice(s->device);
   (void)hipDeviceSynchronize();
   for (int b = 0; b < 2; ++b) {
-    if (s->exec[b]) (void)hipGraphExecDestroy(s->exec[b]);
-    if (s->graph[b]) (void)hipGraphDestroy(s->graph[b]);
+    for (int v = 0; v < 2; ++v) {
+      if (s->exec[b][v]) (void)hipGraphExecDestroy(s->exec[b][v]);
+      if (s->graph[b][v]) (void)hipGraphDestroy(s->graph[b][v]);
+    }
     if (s->htab[b]) (void)hipHostFree(s->htab[b]);
     if (s->dtab[b]) (void)hipFree(s->dtab[b]);
     if (s->step_ev[b]) (void)hipEventDestroy(s->step_ev[b]);

@@ -1,18 +1,20 @@
 // Grouped launches of the serving loop (server.hip).
 //
-// The server advances every resident request by one mode update per
-// scheduler step.  A step is a fixed sequence of launches, each covering
-// the work of all resident requests at once from a device table with one
-// entry per request: the mode-n contraction of every request (grouped
-// contraction), the inversion of every request's V (one workgroup each),
-// F = M V^{-1} for every request (grouped apply) and the normalisation with
-// the new factor's Gram partials (grouped normalise).  Each launch has a
-// fixed grid whose workgroups stride over the step's work items and find
-// their request by a binary search over the entries' first work items, so
-// the step is captured once as a HIP graph and replayed for any set of
-// requests.  A request's work items, plan and summation orders depend only
-// on its own shape, rank, mode and precision, so its result is the same
-// alone and beside any other requests.
+// The server advances every resident request by one CP-ALS sweep per
+// scheduler step.  A step is a fixed sequence of launches, each covering the
+// work of all resident requests at once from a device table with one entry
+// per request and update: for each of the sweep's three updates, the mode-n
+// contraction of every request (grouped contraction), the inversion of
+// every request's V (one workgroup each; inside the contraction launch when
+// every rank fits its LDS, else a parallel branch), F = M V^{-1} for every
+// request (grouped apply) and the normalisation with the new factor's Gram
+// partials (grouped normalise).  Each launch has a fixed grid whose
+// workgroups stride over the step's work items and find their request by a
+// binary search over the entries' first work items, so the step is captured
+// once as a HIP graph and replayed for any set of requests.  A request's
+// work items, plan and summation orders depend only on its own shape, rank,
+// mode and precision, so its result is the same alone and beside any other
+// requests.
 #pragma once
 
 #include "mtk_internal.h"
@@ -62,15 +64,16 @@ struct SrvEntry {
   int64_t nb0;              // first normalise workgroup
 };
 
+// A step's table: entry e[q][u] is request q's update u (mode u) of the sweep.
 struct SrvTable {
   int nreq;
   int pad_;
-  int64_t n_wi, n_ab, n_nb; // work items of the three strided launches
-  SrvEntry e[kSrvMaxReq];
+  int64_t n_wi[3], n_ab[3], n_nb[3];   // work items of the strided launches, per update
+  SrvEntry e[kSrvMaxReq][3];
 };
 
-// Bytes of a table holding n entries (the part the host copies each step).
-inline size_t srv_table_bytes(int n) { return offsetof(SrvTable, e) + (size_t)n * sizeof(SrvEntry); }
+// Bytes of a table holding n requests (the part the host copies each step).
+inline size_t srv_table_bytes(int n) { return offsetof(SrvTable, e) + (size_t)n * 3 * sizeof(SrvEntry); }
 
 // Contraction plan of one request in the grouped step (host): nv = 8, one
 // 16-column tile per workgroup, strided or contiguous reduction; the
@@ -91,11 +94,16 @@ constexpr int kSrvApplyGrid = 1024;
 constexpr int kSrvNormalizeGrid = 1024;
 size_t srv_contract_lds_bytes();
 size_t srv_factor_lds_bytes(int max_rank);
+// Largest rank whose inversion fits the contraction launch's LDS.
+constexpr int kSrvFusedMaxRank = 64;
 
-hipError_t launch_srv_contract(const SrvTable* t, hipStream_t st);
-hipError_t launch_srv_factor(const SrvTable* t, int max_rank, hipStream_t st);
-hipError_t launch_srv_apply(const SrvTable* t, hipStream_t st);
-hipError_t launch_srv_normalize(const SrvTable* t, hipStream_t st);
+// Update u of the step in table t.  with_factor: the contraction launch's
+// first nreq work items invert the requests' V (every R <= kSrvFusedMaxRank);
+// otherwise launch_srv_factor does it.
+hipError_t launch_srv_contract(const SrvTable* t, int u, bool with_factor, hipStream_t st);
+hipError_t launch_srv_factor(const SrvTable* t, int u, int max_rank, hipStream_t st);
+hipError_t launch_srv_apply(const SrvTable* t, int u, hipStream_t st);
+hipError_t launch_srv_normalize(const SrvTable* t, int u, hipStream_t st);
 
 // Device: index of the entry whose work items [first, next first) hold w.
 template <class First>
