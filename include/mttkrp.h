@@ -146,8 +146,8 @@ mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[
  * Every call on one device shares that device's buffer: calls that overlap
  * on one device (any stream, any context) race and must be serialised by
  * the caller.  Returns MTK_EUNSUPPORTED, enqueueing nothing, for a shape
- * whose plan needs more than 64 MiB of scratch (e.g. 768^3 at R = 128 in
- * FP32 / bf16x3 mode 2); every shape up to 1024^3 at R <= 64 fits. */
+ * whose plan needs more than 64 MiB of scratch (large outputs at high rank,
+ * e.g. 2048^3 at R = 128). */
 mtk_status mttkrp_noalloc(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
                           int64_t R, int mode, int prec, float* out, void* stream);
 

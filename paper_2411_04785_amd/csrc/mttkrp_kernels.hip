@@ -35,6 +35,8 @@
 #include "tile_device.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 namespace mtk {
@@ -780,17 +782,23 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 constexpr int64_t kMaxGridX = 0x7fffffff;
 
 // Plan limits (compile-time so a build can be tuned without code changes):
-// widest per-lane reduction run for FP32 / bf16x3, and the workgroup count
-// the outer-loop split aims for.
+// widest per-lane reduction run for FP32 / bf16x3.
 #ifndef MTK_NV_MAX
 #define MTK_NV_MAX 16
-#endif
-#ifndef MTK_WG_TARGET
-#define MTK_WG_TARGET 512
 #endif
 // Largest staged weight block (floats) of a workgroup.
 #ifndef MTK_STAGE_FLOATS
 #define MTK_STAGE_FLOATS 8192
+#endif
+
+// Most 16-column MFMA tiles one FP8 wave holds (its two-term fragment takes
+// 16 VGPRs per tile); waves of a workgroup split wider ranks.
+#ifndef MTK_FP8_NTW
+#define MTK_FP8_NTW 4
+#endif
+// Most fragment VGPRs per lane an FP8 plan gives a wave (sets its nv).
+#ifndef MTK_FP8_FRAG_REGS
+#define MTK_FP8_FRAG_REGS 64
 #endif
 
 // Column length of the padded FP8 fragment codes: every window of the plan.
@@ -798,20 +806,134 @@ inline int frag_red_pad(const ContractPlan& p) { return p.n_rg * p.wr * p.kw; }
 
 }  // namespace
 
-// Spread the outer loop over enough workgroups to fill the 256 CUs (two
-// resident per CU), long enough to amortise each workgroup's fragment load,
-// and keep the partial slices' traffic at a few percent of X (xbytes).
-static void set_loop_blocks(ContractPlan& p, double xbytes) {
+// The kernel a plan launches, for its occupancy.  A contiguous plan stands
+// for its 16-byte-load form and a strided one for the strided form, so the
+// plan -- and with it the summation order -- does not depend on the
+// tensor's alignment.
+template <int PREC, int NT>
+const void* kernel_of_nt(const ContractPlan& p) {
+  if constexpr (PREC != MTK_FP8_E4M3) {
+    if (p.cm) return reinterpret_cast<const void*>(&contract_cm_kernel<PREC, NT, 8>);
+  }
+  const bool c = p.sRed == 1;
+  auto pick = [&](auto nv_tag) -> const void* {
+    constexpr int NV = decltype(nv_tag)::value;
+    if (c) return reinterpret_cast<const void*>(&contract_kernel<PREC, NT, NV, true, true>);
+    return reinterpret_cast<const void*>(&contract_kernel<PREC, NT, NV, false, false>);
+  };
+  if constexpr (PREC == MTK_FP8_E4M3) {
+    if (p.nv == 32) return pick(std::integral_constant<int, 32>{});
+    if constexpr (NT <= 2) if (p.nv == 64) return pick(std::integral_constant<int, 64>{});
+    if constexpr (NT <= 1) if (p.nv == 128) return pick(std::integral_constant<int, 128>{});
+  } else {
+    if (p.nv == 8) return pick(std::integral_constant<int, 8>{});
+    if constexpr (NT <= 4) if (p.nv == 16) return pick(std::integral_constant<int, 16>{});
+    if constexpr (NT <= 2) if (p.nv == 32) return pick(std::integral_constant<int, 32>{});
+    if constexpr (NT <= 1) if (p.nv == 64) return pick(std::integral_constant<int, 64>{});
+  }
+  return nullptr;
+}
+
+template <int PREC>
+const void* kernel_of_prec(const ContractPlan& p) {
+  switch (p.ntw) {
+    case 1: return kernel_of_nt<PREC, 1>(p);
+    case 2: return kernel_of_nt<PREC, 2>(p);
+    case 3: return kernel_of_nt<PREC, 3>(p);
+    case 4: return kernel_of_nt<PREC, 4>(p);
+  }
+  if constexpr (PREC != MTK_FP8_E4M3) {
+    switch (p.ntw) {
+      case 5: return kernel_of_nt<PREC, 5>(p);
+      case 6: return kernel_of_nt<PREC, 6>(p);
+      case 7: return kernel_of_nt<PREC, 7>(p);
+      case 8: return kernel_of_nt<PREC, 8>(p);
+    }
+  }
+  return nullptr;
+}
+
+// Resident workgroups per CU of a plan's kernel (its registers and the
+// largest LDS a plan gives it) and the device's CU count, looked up once per
+// kernel.  Two per CU on 256 CUs if the runtime cannot tell (no device).
+struct Slots {
+  int64_t cus, per_cu;
+};
+Slots plan_slots(const ContractPlan& p, int prec) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, size_t>, Slots> cache;
+  const void* k = prec == MTK_FP32 ? kernel_of_prec<MTK_FP32>(p)
+                  : prec == MTK_BF16X3 ? kernel_of_prec<MTK_BF16X3>(p) : kernel_of_prec<MTK_FP8_E4M3>(p);
+  // LDS at the largest loop block: staged weights plus the wave-sum area.
+  const size_t red = p.cm ? (size_t)4 * 16 * p.ntw * 64 : (p.wr > 1 ? (size_t)4 * p.ntw * 4 * 64 : 0);
+  const size_t lds = ((size_t)std::max(1, MTK_STAGE_FLOATS / p.R) * p.R + red) * sizeof(float);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({k, lds});
+  if (it != cache.end()) return it->second;
+  Slots sl{256, 2};
+  int dev = 0, cus = 0, per_cu = 0;
+  if (k && hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds) == hipSuccess && cus > 0 && per_cu > 0) {
+    sl = Slots{cus, per_cu};
+  } else {
+    (void)hipGetLastError();
+  }
+  cache[{k, lds}] = sl;
+  return sl;
+}
+
+// Split the outer loop into blocks, by a cost model in units of one
+// workgroup loop iteration.  Workgroups spread evenly over the CUs; a CU
+// runs up to per_cu of them at once, in rounds, and its stream saturates at
+// about two resident workgroups (eight waves).  So a CU with c workgroups
+// at once takes rounds x (loop block + ~4 iterations of prologue: fragment
+// load, weight staging, epilogue) x c / min(c, 2), and the split-K partial
+// slices (written, then read by the reduction) add their bytes at the
+// saturated rate.  The cheapest block count wins, fewer slices on ties;
+// the staged weights must fit their LDS budget.
+static void set_loop_blocks(ContractPlan& p, int prec, Slots sl) {
   const int64_t base = (int64_t)p.n_rg * p.n_mg;
-  const int64_t target = MTK_WG_TARGET;
-  int64_t n_lb = std::max<int64_t>(1, std::min<int64_t>(p.nLoop, cdiv(target, base)));
-  const double slice_bytes = (double)p.nM * p.R * 4.0 * 2.0;
-  const double cap = std::max(0.03 * xbytes, 4.0 * 1024 * 1024);
-  while (n_lb > 1 && (double)p.n_rg * n_lb * slice_bytes > cap) n_lb = cdiv(n_lb, 2);
-  p.loop_block = (int)cdiv(p.nLoop, n_lb);
-  p.loop_block = std::min(p.loop_block, std::max(1, MTK_STAGE_FLOATS / p.R));   // staged weights
+  const int64_t lb_cap = std::max(1, MTK_STAGE_FLOATS / p.R);
+  const double elem = prec == MTK_FP8_E4M3 ? 1.0 : 4.0;
+  // Bytes of X a workgroup reads per loop iteration.
+  const double it_bytes = (p.cm ? 64.0 : 16.0) * p.mt_per_wg * p.wr * p.kw * elem;
+  const double slice_bytes = 2.0 * p.nM * p.R * 4.0;
+  constexpr double kSat = 2.0, kPrologue = 4.0;
+  const int64_t max_blocks = std::min<int64_t>(p.nLoop, std::max<int64_t>(1, 16 * sl.cus * sl.per_cu / base + 1));
+  int64_t best_n = 0;
+  double best_cost = 0.0;
+  for (int64_t n = 1; n <= max_blocks; ++n) {
+    const int64_t lb = cdiv(p.nLoop, n);
+    if (lb > lb_cap) continue;
+    const int64_t nb = cdiv(p.nLoop, lb);
+    if (nb != n) continue;                                   // same split as a smaller n
+    const int64_t grid = base * nb;
+    if (grid + 1 > kMaxGridX) break;
+    const int64_t per_cu = cdiv(grid, sl.cus);
+    const int64_t conc = std::min(per_cu, sl.per_cu);
+    const int64_t rounds = cdiv(per_cu, sl.per_cu);
+    double cost = rounds * (lb + kPrologue) * conc / std::min<double>(conc, kSat);
+    if (p.n_rg * nb > 1) cost += p.n_rg * nb * slice_bytes / (sl.cus * kSat * it_bytes);
+    if (best_n == 0 || cost < best_cost) { best_n = nb; best_cost = cost; }
+  }
+  if (best_n == 0) best_n = cdiv(p.nLoop, lb_cap);          // the weight budget forces the split
+  p.loop_block = (int)cdiv(p.nLoop, best_n);
   p.n_lb = (int)cdiv(p.nLoop, p.loop_block);
   p.slices = p.n_rg * p.n_lb;
+}
+
+// Waves of a workgroup along a contiguous reduction of `windows` windows:
+// the largest of 4, 2, 1 (at most wmax) that leaves the fewest windows past
+// the end idle.
+static int pick_wr(int64_t windows, int wmax) {
+  int best = 1;
+  int64_t best_idle = -1;
+  for (int wr = std::min(4, wmax); wr >= 1; wr /= 2) {
+    const int64_t idle = cdiv(windows, wr) * wr - windows;
+    if (best_idle < 0 || idle < best_idle) { best = wr; best_idle = idle; }
+  }
+  return best;
 }
 
 ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_aligned16, bool transposed) {
@@ -821,7 +943,7 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
   p.nt = (int)cdiv(R, 16);
   // FP8 needs 32 reduction values per lane per MFMA; above 64 columns two
   // waves split R over the same X tile so the fragments stay in registers.
-  p.ncg = (prec == MTK_FP8_E4M3 && p.nt > 4) ? 2 : 1;
+  p.ncg = (prec == MTK_FP8_E4M3 && p.nt > MTK_FP8_NTW) ? (int)cdiv(p.nt, MTK_FP8_NTW) : 1;
   p.ntw = (int)cdiv(p.nt, p.ncg);
   if (mode == 0) { p.nM = (int)I; p.nRed = (int)K; p.nLoop = (int)J; p.sM = J * K; p.sRed = 1; p.sLoop = K; }
   else if (mode == 1) { p.nM = (int)J; p.nRed = (int)K; p.nLoop = (int)I; p.sM = K; p.sRed = 1; p.sLoop = J * K; }
@@ -837,12 +959,12 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
     p.nv = 8;
     p.kw = 32;
     const int64_t windows = cdiv(p.nRed, p.kw);
-    p.wr = std::min<int>(4 / p.ncg, windows >= 4 ? 4 : (windows >= 2 ? 2 : 1));
+    p.wr = pick_wr(windows, 4 / p.ncg);
     p.mt_per_wg = 4 / (p.ncg * p.wr);
     p.n_rg = (int)cdiv(p.nRed, (int64_t)p.wr * p.kw);
     p.n_mg = (int)cdiv(cdiv(p.nM, 64), p.mt_per_wg);
-    set_loop_blocks(p, I * J * K * 4.0);
     p.vec = true;
+    set_loop_blocks(p, prec, plan_slots(p, prec));
     return p;
   }
 
@@ -850,7 +972,7 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
   int nv;
   if (prec == MTK_FP8_E4M3) {
     nv = 128;
-    while (nv > 32 && p.ntw * nv / 2 > 64) nv /= 2;      // hi + lo terms
+    while (nv > 32 && p.ntw * nv / 2 > MTK_FP8_FRAG_REGS) nv /= 2;      // hi + lo terms
     while (nv > 32 && 4 * (nv / 2) >= p.nRed) nv /= 2;
   } else {
     nv = MTK_NV_MAX;
@@ -861,17 +983,12 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
   p.kw = 4 * nv;
   const int64_t windows = cdiv(p.nRed, p.kw);
   const int wmax = 4 / p.ncg;
-  if (p.sRed == 1) {
-    p.wr = windows >= 4 ? 4 : (windows >= 2 ? 2 : 1);
-    p.wr = std::min(p.wr, wmax);
-  } else {
-    p.wr = 1;
-  }
+  p.wr = p.sRed == 1 ? pick_wr(windows, wmax) : 1;
   p.mt_per_wg = 4 / (p.ncg * p.wr);
   p.n_rg = (int)cdiv(p.nRed, (int64_t)p.wr * p.kw);
   p.n_mg = (int)cdiv(cdiv(p.nM, 16), p.mt_per_wg);
 
-  set_loop_blocks(p, (double)I * J * K * (prec == MTK_FP8_E4M3 ? 1.0 : 4.0));
+  set_loop_blocks(p, prec, plan_slots(p, prec));
   const int elem = prec == MTK_FP8_E4M3 ? 1 : 4;
   p.vec = (p.sRed == 1) && x_aligned16 && ((int64_t)p.nRed * elem % 16 == 0);
   return p;

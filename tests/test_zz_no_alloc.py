@@ -65,16 +65,17 @@ def test_noalloc_matches_mttkrp_twice(ctx, prec):
 
 
 def test_noalloc_refuses_oversized_plan(ctx):
-    # 768 x 768 x 768 at R = 128, FP32 mode 2, needs 108 MiB of partial
-    # slices: refused with MTK_EUNSUPPORTED; the output is left untouched.
-    # Only descriptors are built: the (unread) tensor is a 4-byte buffer.
+    # 2048 x 2048 x 2048 at R = 128, FP32 mode 2, needs far more than 64 MiB
+    # of partial slices: refused with MTK_EUNSUPPORTED; the output is left
+    # untouched.  Only descriptors are built: the (unread) tensor is a 4-byte
+    # buffer.
     import ctypes
     import torch
     from paper_2411_04785_amd.mttkrp import MtkError, MTK_EUNSUPPORTED, Tensor, _dims, _stream
     buf = torch.zeros(1, dtype=torch.float32, device="cuda")
-    f = torch.zeros((768, 128), dtype=torch.float32, device="cuda")
-    out = torch.full((768, 128), 7.0, dtype=torch.float32, device="cuda")
-    d = Tensor(buf.data_ptr(), None, _dims((768, 768, 768)), 0, None)
+    f = torch.zeros((2048, 128), dtype=torch.float32, device="cuda")
+    out = torch.full((2048, 128), 7.0, dtype=torch.float32, device="cuda")
+    d = Tensor(buf.data_ptr(), None, _dims((2048, 2048, 2048)), 0, None)
     fp = (ctypes.c_void_p * 3)(f.data_ptr(), f.data_ptr(), f.data_ptr())
     st = ctx._L.mttkrp_noalloc(ctx.h, ctypes.byref(d), fp, 128, 2, 0, out.data_ptr(), _stream())
     assert st == MTK_EUNSUPPORTED
