@@ -95,3 +95,51 @@ def mttkrp_brute(X: np.ndarray, factors: Sequence[np.ndarray], mode: int) -> np.
                     else:
                         out[k, r] += x * A[i, r] * B[j, r]
     return out
+
+
+def khatri_rao_many(mats: Sequence[np.ndarray]) -> np.ndarray:
+    """Column-wise Khatri-Rao product of several matrices, the first one's row
+    index slowest: row (p, q, ..., z) -> P(p, :) * Q(q, :) * ... * Z(z, :)."""
+    out = np.asarray(mats[0], dtype=np.float64)
+    for M in mats[1:]:
+        out = khatri_rao(out, M)
+    return out
+
+
+def unfold_nway(X: np.ndarray, mode: int) -> np.ndarray:
+    """Mode-n unfolding of an N-way tensor in FP64: rows = index of ``mode``,
+    columns = the other indices in increasing mode order, the earliest
+    slowest (the same convention as :func:`unfold`)."""
+    X = np.asarray(X, dtype=np.float64)
+    order = [mode] + [m for m in range(X.ndim) if m != mode]
+    return np.transpose(X, order).reshape(X.shape[mode], -1)
+
+
+def mttkrp_nway(X: np.ndarray, factors: Sequence[np.ndarray], mode: int) -> np.ndarray:
+    """FP64 mode-n MTTKRP of an N-way tensor (N >= 2):
+    M_n(i_n, r) = sum over all other indices of X(i_1, ..., i_N) prod_{m != n} A_m(i_m, r),
+    computed as the unfolding times the Khatri-Rao product of the other factors
+    (same pairing of unfolding column and Khatri-Rao row as for three ways)."""
+    X = np.asarray(X)
+    if not 0 <= mode < X.ndim:
+        raise ValueError("mode out of range")
+    others = [factors[m] for m in range(X.ndim) if m != mode]
+    return unfold_nway(X, mode) @ khatri_rao_many(others)
+
+
+def mttkrp_nway_brute(X: np.ndarray, factors: Sequence[np.ndarray], mode: int) -> np.ndarray:
+    """Plain loops over every element of X and every column r of the N-way
+    definition.  Pure Python, for tiny inputs only."""
+    X = np.asarray(X, dtype=np.float64)
+    F = [np.asarray(f, dtype=np.float64) for f in factors]
+    R = F[0].shape[1]
+    out = np.zeros((X.shape[mode], R))
+    for idx in np.ndindex(*X.shape):
+        x = float(X[idx])
+        for r in range(R):
+            p = x
+            for m, i in enumerate(idx):
+                if m != mode:
+                    p *= F[m][i, r]
+            out[idx[mode], r] += p
+    return out

@@ -395,3 +395,57 @@ def test_pins_catch_wrong_tie_rule():
     away = np.searchsorted(pos, mids, side="right")      # ties away from zero
     ref = torch.from_numpy(mids.astype(np.float32)).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
     assert not np.array_equal(away.astype(np.uint8), ref)
+
+
+# ----------------------------------------------------------- N-way MTTKRP ---
+
+@pytest.mark.parametrize("dims", [(3, 2, 4, 2), (2, 3, 2, 2, 3), (4, 1, 3, 2)])
+def test_mttkrp_nway_matches_brute_force(dims):
+    g = np.random.default_rng(len(dims))
+    X = g.standard_normal(dims)
+    facs = [g.standard_normal((d, 3)) for d in dims]
+    for mode in range(len(dims)):
+        assert rel(oracle.mttkrp_nway(X, facs, mode), oracle.mttkrp_nway_brute(X, facs, mode)) < 1e-13
+
+
+def test_mttkrp_nway_three_way_is_the_three_way_definition():
+    X, facs = rand_case((5, 4, 6), 3, seed=21)
+    for mode in range(3):
+        assert rel(oracle.mttkrp_nway(X, facs, mode), oracle.mttkrp_brute(X, facs, mode)) < 1e-13
+
+
+def test_mttkrp_nway_closed_form_exact_cp():
+    # X = [[A_1, ..., A_4]] gives M_n = A_n (*_{m != n} A_m^T A_m).
+    g = np.random.default_rng(8)
+    dims, R = (5, 6, 4, 7), 3
+    facs = [g.standard_normal((d, R)) for d in dims]
+    X = np.einsum("ir,jr,kr,lr->ijkl", *facs)
+    for mode in range(4):
+        V = np.ones((R, R))
+        for m in range(4):
+            if m != mode:
+                V *= facs[m].T @ facs[m]
+        assert rel(oracle.mttkrp_nway(X, facs, mode), facs[mode] @ V) < 1e-12
+
+
+def test_mttkrp_nway_unit_mode_reduces_order():
+    # A mode of size 1 with factor row a: the 4-way MTTKRP equals the 3-way
+    # one of the squeezed tensor with the other factors' rows scaled by a.
+    g = np.random.default_rng(9)
+    X3 = g.standard_normal((4, 5, 6))
+    facs3 = [g.standard_normal((d, 2)) for d in X3.shape]
+    a = g.standard_normal((1, 2))
+    X4 = X3[:, :, None, :]
+    facs4 = [facs3[0], facs3[1], a, facs3[2]]
+    for m4, m3 in ((0, 0), (1, 1), (3, 2)):
+        assert rel(oracle.mttkrp_nway(X4, facs4, m4), oracle.mttkrp(X3, facs3, m3) * a) < 1e-13
+
+
+def test_pins_catch_reversed_nway_khatri_rao():
+    # The Khatri-Rao order must follow the unfolding's column order.
+    g = np.random.default_rng(10)
+    X = g.standard_normal((3, 2, 4, 2))
+    facs = [g.standard_normal((d, 2)) for d in X.shape]
+    others = [facs[m] for m in range(4) if m != 1]
+    wrong = oracle.unfold_nway(X, 1) @ oracle.khatri_rao_many(others[::-1])
+    assert rel(wrong, oracle.mttkrp_nway_brute(X, facs, 1)) > 1e-3
