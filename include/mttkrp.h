@@ -151,6 +151,29 @@ mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[
 mtk_status mttkrp_noalloc(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
                           int64_t R, int mode, int prec, float* out, void* stream);
 
+/* Mode-n MTTKRP of a dense N-way tensor (3 <= N <= 8), FP32 in memory:
+ *     M(i_n, r) = sum over all other indices of X(i_1, ..., i_N)
+ *                 * prod_{m != n} A_m(i_m, r)
+ * (the tensor unfolded along mode n times the Khatri-Rao product of the
+ * other N-1 factors; the standard definition, which the paper does not
+ * state).  The row-major bytes of X are viewed as a three-way tensor that
+ * merges consecutive modes -- (P, d_n, Q) for a middle mode, with the first
+ * and last modes splitting the others into two groups of balanced size --
+ * and a merged group's factor is the Khatri-Rao product of its factors
+ * (first mode's index slowest), formed in FP32 in the context's workspace;
+ * the three-way contraction then runs as mttkrp does.  With N = 3 the result
+ * is mttkrp's, bit for bit.
+ *  X       : device FP32, element (i_1..i_N) at ((i_1 d_2 + i_2) d_3 + ...) .
+ *  dims    : host int64[nmodes], each >= 1, product < 2^40, and every merged
+ *            group's product <= 2^30 (else MTK_EUNSUPPORTED).
+ *  factors : host array of nmodes device pointers (dims[m] x R, FP32,
+ *            row-major); factors[mode] is not read and may be NULL.
+ *  prec    : MTK_FP32 or MTK_BF16X3.
+ *  R, mode, out, stream : as for mttkrp (out is dims[mode] x R). */
+mtk_status mttkrp_nway(mtk_ctx* ctx, const float* X, int nmodes, const int64_t* dims,
+                       const float* const* factors, int64_t R, int mode, int prec, float* out,
+                       void* stream);
+
 /* Mode-0 or mode-1 MTTKRP by the dimension tree, the form als_sweep uses
  * for those two updates when mtk_sweep_uses_dimtree says so.  First
  * Y = X x_3 C, Y(i,j,r) = sum_k X(i,j,k) C(k,r) (an I*J x R FP32

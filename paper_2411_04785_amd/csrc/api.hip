@@ -348,6 +348,88 @@ mtk_status mttkrp_noalloc(mtk_ctx* c, const mtk_tensor* X, const float* const fa
   return mttkrp_impl(c, X, factors, (int)R, mode, prec, out, c->scratch, static_cast<hipStream_t>(stream));
 }
 
+// The three-way view of an N-way mode-n MTTKRP: dimensions (v[0], v[1],
+// v[2]), the output's position vm in it, and for the two other positions
+// the range of original modes [lo, hi) merged into them (one mode: its own
+// factor; several: their Khatri-Rao product).  A first or last mode splits
+// the other modes into two groups of balanced size.
+struct NwayView {
+  int64_t v[3];
+  int vm;
+  int lo[3], hi[3];
+};
+
+static NwayView nway_view(int n, const int64_t* d, int mode) {
+  NwayView w{};
+  auto prod = [&](int a, int b) { int64_t p = 1; for (int m = a; m < b; ++m) p *= d[m]; return p; };
+  auto split = [&](int a, int b) {           // cut [a, b) at s, a < s < b, balancing the products
+    int best = a + 1;
+    double bd = 1e300;
+    for (int s = a + 1; s < b; ++s) {
+      const double x = std::fabs(std::log((double)prod(a, s)) - std::log((double)prod(s, b)));
+      if (x < bd) { bd = x; best = s; }
+    }
+    return best;
+  };
+  if (mode == 0) {
+    const int s = split(1, n);
+    w.vm = 0; w.lo[0] = 0; w.hi[0] = 1; w.lo[1] = 1; w.hi[1] = s; w.lo[2] = s; w.hi[2] = n;
+  } else if (mode == n - 1) {
+    const int s = split(0, n - 1);
+    w.vm = 2; w.lo[0] = 0; w.hi[0] = s; w.lo[1] = s; w.hi[1] = n - 1; w.lo[2] = n - 1; w.hi[2] = n;
+  } else {
+    w.vm = 1; w.lo[0] = 0; w.hi[0] = mode; w.lo[1] = mode; w.hi[1] = mode + 1; w.lo[2] = mode + 1; w.hi[2] = n;
+  }
+  for (int p = 0; p < 3; ++p) w.v[p] = prod(w.lo[p], w.hi[p]);
+  return w;
+}
+
+mtk_status mttkrp_nway(mtk_ctx* c, const float* X, int nmodes, const int64_t* dims, const float* const* factors,
+                       int64_t R, int mode, int prec, float* out, void* stream) {
+  if (!c) return MTK_EINVAL;
+  if (!X || !dims || !factors || !out) return fail(c, MTK_EINVAL, "NULL argument");
+  if (nmodes < 3 || nmodes > mtk::kMaxNwayModes) return fail(c, MTK_EINVAL, "nmodes must be in [3, 8]");
+  if (mode < 0 || mode >= nmodes) return fail(c, MTK_EINVAL, "mode out of range");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  if (prec != MTK_FP32 && prec != MTK_BF16X3) return fail(c, MTK_EINVAL, "mttkrp_nway: prec must be MTK_FP32 or MTK_BF16X3");
+  if (reinterpret_cast<uintptr_t>(X) & 3) return fail(c, MTK_EINVAL, "X not 4-byte aligned");
+  double total = 1.0;
+  for (int m = 0; m < nmodes; ++m) {
+    if (dims[m] < 1 || dims[m] > (1 << 30)) return fail(c, MTK_EINVAL, "dims out of range");
+    total *= (double)dims[m];
+    if (m != mode && !factors[m]) return fail(c, MTK_EINVAL, "NULL factor pointer");
+  }
+  if (total >= 1099511627776.0) return fail(c, MTK_EINVAL, "tensor has 2^40 elements or more");
+  const NwayView w = nway_view(nmodes, dims, mode);
+  for (int p = 0; p < 3; ++p)
+    if (w.v[p] > (1 << 30)) return fail(c, MTK_EUNSUPPORTED, "mttkrp_nway: a merged dimension exceeds 2^30");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // Workspace: the merged groups' Khatri-Rao products, then the contraction's.
+  size_t kr_bytes[3] = {0, 0, 0};
+  for (int p = 0; p < 3; ++p)
+    if (p != w.vm && w.hi[p] - w.lo[p] > 1) kr_bytes[p] = round256((size_t)w.v[p] * R * sizeof(float));
+  mtk_tensor t3{X, nullptr, {w.v[0], w.v[1], w.v[2]}, MTK_FP32, nullptr};
+  const size_t need = kr_bytes[0] + kr_bytes[1] + kr_bytes[2] + mttkrp_ws(t3.dims, (int)R, w.vm, prec);
+  mtk_status s = ensure_ws(c, need, st);
+  if (s != MTK_OK) return s;
+  char* wp = static_cast<char*>(c->ws);
+  const float* f3[3] = {nullptr, nullptr, nullptr};
+  for (int p = 0; p < 3; ++p) {
+    if (p == w.vm) continue;
+    if (w.hi[p] - w.lo[p] == 1) {
+      f3[p] = factors[w.lo[p]];
+      continue;
+    }
+    float* kr = reinterpret_cast<float*>(wp);
+    wp += kr_bytes[p];
+    hipError_t e = mtk::launch_kr_rows(factors + w.lo[p], dims + w.lo[p], w.hi[p] - w.lo[p], (int)R, kr, st);
+    if (e != hipSuccess) return hip_fail(c, e, "Khatri-Rao launch");
+    f3[p] = kr;
+  }
+  return mttkrp_impl(c, &t3, f3, (int)R, w.vm, prec, out, wp, st);
+}
+
 mtk_status mttkrp_dimtree(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], int64_t R, int mode,
                           int prec, float* out, void* stream) {
   if (!c) return MTK_EINVAL;

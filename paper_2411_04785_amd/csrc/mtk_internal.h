@@ -101,6 +101,12 @@ hipError_t launch_dimtree_mttkrp(int mode, bool form_y, const float* X, bool x_a
                                  const float* const factors[3], int R, int prec, float* out, void* ws,
                                  hipStream_t st, const FactorArgs* job, MSlices* defer = nullptr);
 
+// N-way MTTKRP (nway.hip): Khatri-Rao product of n consecutive modes'
+// factors (first mode's index slowest), rows = prod dims, into out (rows x R).
+constexpr int kMaxNwayModes = 8;
+hipError_t launch_kr_rows(const float* const* factors, const int64_t* dims, int n, int R, float* out,
+                          hipStream_t st);
+
 // FP8 tensor preparation (per mode-1 slice power-of-two scaled e4m3).
 hipError_t launch_quantize_slices(const float* x, int64_t I, int64_t J, int64_t K, uint8_t* q,
                                   uint8_t* qt, int32_t* exps, hipStream_t st);

