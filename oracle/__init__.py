@@ -17,7 +17,8 @@ the standard mathematical definition, written out directly in FP64:
   other two factors, ``M_1 = X_(1) (B kr C)``; entrywise
   ``M_1(i,r) = sum_{j,k} X(i,j,k) B(j,r) C(k,r)`` (likewise for modes 2, 3),
   and for an N-way tensor the same with the product of the N-1 other
-  factors (``mttkrp_nway``).
+  factors (``mttkrp_nway``); for a sparse tensor in coordinates, the same sum
+  over the stored entries (``mttkrp_coo``).
 * CP-ALS: block coordinate descent on ``||X - [[lambda; A, B, C]]||_F``,
   each factor solved from its normal equations ``A_n V = M_n`` with
   ``V = *_{m != n} A_m^T A_m`` (Hadamard product of Grams).
@@ -31,7 +32,7 @@ that reduce to library routines, invariants and library casts -- in
 """
 
 from .mttkrp import khatri_rao, unfold, mttkrp, mttkrp_rows, mttkrp_brute  # noqa: F401
-from .mttkrp import khatri_rao_many, unfold_nway, mttkrp_nway, mttkrp_nway_brute  # noqa: F401
+from .mttkrp import khatri_rao_many, unfold_nway, mttkrp_nway, mttkrp_nway_brute, mttkrp_coo  # noqa: F401
 from .cpals import (gram_hadamard, gram_solve, normalize_columns, cp_als,  # noqa: F401
                     reconstruct_slices, fit)
 from .formats import (bf16_round, bf16x2_split, e4m3_values, e4m3_encode,  # noqa: F401

@@ -143,3 +143,20 @@ def mttkrp_nway_brute(X: np.ndarray, factors: Sequence[np.ndarray], mode: int) -
                     p *= F[m][i, r]
             out[idx[mode], r] += p
     return out
+
+
+def mttkrp_coo(idx: Sequence[np.ndarray], vals: np.ndarray, dims: Sequence[int],
+               factors: Sequence[np.ndarray], mode: int) -> np.ndarray:
+    """FP64 mode-n MTTKRP of a sparse 3-way tensor given as coordinates
+    (idx[0][e], idx[1][e], idx[2][e]) and values vals[e]; repeated
+    coordinates add.  Each nonzero contributes vals[e] times the product of
+    the other two factors' rows to output row idx[mode][e] -- the dense
+    definition restricted to the stored entries."""
+    F = [np.asarray(f, dtype=np.float64) for f in factors]
+    R = F[0].shape[1]
+    v = np.asarray(vals, dtype=np.float64)
+    others = [m for m in range(3) if m != mode]
+    contrib = v[:, None] * F[others[0]][np.asarray(idx[others[0]])] * F[others[1]][np.asarray(idx[others[1]])]
+    out = np.zeros((int(dims[mode]), R))
+    np.add.at(out, np.asarray(idx[mode]), contrib)
+    return out

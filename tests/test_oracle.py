@@ -449,3 +449,52 @@ def test_pins_catch_reversed_nway_khatri_rao():
     others = [facs[m] for m in range(4) if m != 1]
     wrong = oracle.unfold_nway(X, 1) @ oracle.khatri_rao_many(others[::-1])
     assert rel(wrong, oracle.mttkrp_nway_brute(X, facs, 1)) > 1e-3
+
+
+# ---------------------------------------------------------- sparse MTTKRP ---
+
+def _coo_case(dims, nnz, R, seed, dup=True):
+    g = np.random.default_rng(seed)
+    idx = [g.integers(0, d, nnz) for d in dims]
+    if dup:                                   # a repeated coordinate adds
+        for m in range(3):
+            idx[m][-1] = idx[m][0]
+    vals = g.standard_normal(nnz)
+    facs = [g.standard_normal((d, R)) for d in dims]
+    return idx, vals, facs
+
+
+def _densify(idx, vals, dims):
+    X = np.zeros(dims)
+    np.add.at(X, tuple(idx), vals)
+    return X
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_mttkrp_coo_equals_dense_definition(mode):
+    dims = (9, 7, 11)
+    idx, vals, facs = _coo_case(dims, 120, 4, seed=30 + mode)
+    X = _densify(idx, vals, dims)
+    assert rel(oracle.mttkrp_coo(idx, vals, dims, facs, mode), oracle.mttkrp_brute(X, facs, mode)) < 1e-13
+
+
+def test_mttkrp_coo_single_entry_closed_form():
+    # One nonzero v at (i, j, k): row i of M_1 is v * B(j,:) * C(k,:), all else 0.
+    g = np.random.default_rng(31)
+    facs = [g.standard_normal((d, 3)) for d in (4, 5, 6)]
+    M = oracle.mttkrp_coo([np.array([2]), np.array([3]), np.array([1])], np.array([1.5]), (4, 5, 6), facs, 0)
+    want = np.zeros((4, 3))
+    want[2] = 1.5 * facs[1][3] * facs[2][1]
+    assert np.array_equal(M, want)
+
+
+def test_pins_catch_coo_factor_swap():
+    dims = (6, 8, 5)
+    idx, vals, facs = _coo_case(dims, 60, 3, seed=32)
+    X = _densify(idx, vals, dims)
+    wrong = oracle.mttkrp_coo([idx[0], idx[2], idx[1]], vals, (6, 5, 8), [facs[0], facs[2], facs[1]], 0)
+    assert rel(wrong, oracle.mttkrp_brute(X, facs, 0)) < 1e-13      # a consistent relabelling is harmless
+    bad = vals[:, None] * facs[1][idx[2] % 8] * facs[2][idx[1] % 5]
+    out = np.zeros((6, 3))
+    np.add.at(out, idx[0], bad)
+    assert rel(out, oracle.mttkrp_brute(X, facs, 0)) > 1e-3         # crossed indices are caught
