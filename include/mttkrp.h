@@ -174,6 +174,48 @@ mtk_status mttkrp_nway(mtk_ctx* ctx, const float* X, int nmodes, const int64_t* 
                        const float* const* factors, int64_t R, int mode, int prec, float* out,
                        void* stream);
 
+/* Sparse three-way tensors in coordinate form.
+ *
+ * A sparse tensor is a list of nnz stored entries (i, j, k, v); repeated
+ * coordinates add.  Its mode-n MTTKRP is the dense definition above with the
+ * sum restricted to the stored entries, e.g. for mode 0
+ *     M(i,r) = sum over entries (i, j, k, v) of v B(j,r) C(k,r)
+ * (the standard definition; the paper has no passage on sparse tensors). */
+typedef struct mtk_coo mtk_coo;
+
+/* Copy the entries to the device in the library's form: for each mode, the
+ * entries sorted by that mode's index (stable, so entries with equal index
+ * keep their input order), 16 bytes each, plus the carry slots mttkrp_coo
+ * uses -- about 48 bytes per entry in one allocation, freed by
+ * mtk_coo_destroy.  The sort runs on `stream`, which is synchronised before
+ * the call returns; the caller's arrays may be freed afterwards.
+ *  dims   : host int64[3], each in [1, 2^31 - 1].
+ *  nnz    : number of entries, 0 <= nnz < 2^31.
+ *  idx    : host array of three device int32 arrays (nnz each, 4-byte
+ *           aligned): the i, j and k index of every entry.
+ *  vals   : device FP32[nnz] values.
+ *  out    : receives the handle (NULL on failure).
+ * MTK_EINVAL (nothing kept) if an index lies outside dims; MTK_ENOMEM if the
+ * device allocation fails. */
+mtk_status mtk_coo_create(mtk_ctx* ctx, const int64_t dims[3], int64_t nnz, const int32_t* const idx[3],
+                          const float* vals, void* stream, mtk_coo** out);
+/* Free a tensor made by mtk_coo_create (synchronises its device).  NULL is a no-op. */
+mtk_status mtk_coo_destroy(mtk_coo* t);
+/* Number of stored entries of t, or -1 for NULL. */
+int64_t mtk_coo_nnz(const mtk_coo* t);
+
+/* Mode-n MTTKRP of a sparse tensor, FP32 products and sums.  Each output row
+ * is the sum of its entries' terms in entry order (the sorted order), cut
+ * into segments of a length that depends on nnz only, the segments' partial
+ * sums then added in order: the result is deterministic.
+ *  factors : the two factors other than `mode` are read (device FP32,
+ *            dims[m] x R row-major); factors[mode] may be NULL.
+ *  R       : 1..128.  out : device FP32, dims[mode] x R, overwritten.
+ * Calls on one mtk_coo must not overlap in time (they share its carry
+ * slots); calls on different tensors may. */
+mtk_status mttkrp_coo(mtk_ctx* ctx, const mtk_coo* t, const float* const factors[3], int64_t R, int mode,
+                      float* out, void* stream);
+
 /* Mode-0 or mode-1 MTTKRP by the dimension tree, the form als_sweep uses
  * for those two updates when mtk_sweep_uses_dimtree says so.  First
  * Y = X x_3 C, Y(i,j,r) = sum_k X(i,j,k) C(k,r) (an I*J x R FP32

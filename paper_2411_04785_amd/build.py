@@ -27,7 +27,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
           f"-I{os.path.join(ROOT, 'include')}"]
 
-SOURCES = ["mttkrp_kernels.hip", "dimtree.hip", "als_kernels.hip", "quant_kernels.hip", "nway.hip", "api.hip",
+SOURCES = ["mttkrp_kernels.hip", "dimtree.hip", "als_kernels.hip", "quant_kernels.hip", "nway.hip", "sparse.hip", "api.hip",
            "server.hip"]
 
 

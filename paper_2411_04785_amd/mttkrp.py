@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "MTK_OK", -1: "MTK_EINVAL", -2: "MTK_ENOMEM", -3: "MTK_EHIP",
                 -5: "MTK_EUNSUPPORTED", -6: "MTK_EBUDGET", -7: "MTK_EAGAIN"}
 
 EXPORTED = ["mtk_create", "mtk_destroy", "mtk_last_error", "mtk_check", "mtk_reserve",
-            "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_nway", "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
+            "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_nway", "mtk_coo_create", "mtk_coo_destroy", "mtk_coo_nnz", "mttkrp_coo",
+            "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
             "als_sweep", "als_run", "mtk_graph_reset",
             "mtk_server_create", "mtk_server_submit", "mtk_server_poll", "mtk_server_stats",
             "mtk_server_request_bytes", "mtk_server_destroy"]
@@ -69,6 +70,10 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise FileNotFoundError(f"{LIB_PATH} not built: run `python -m paper_2411_04785_amd.build`")
+    # torch carries its own HIP runtime under the same soname as the system
+    # one the library links against; whichever is loaded first serves the
+    # process, and torch finds no device on the other.  Load torch's first.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     P3 = ctypes.c_void_p * 3
@@ -82,6 +87,10 @@ def lib() -> ctypes.CDLL:
         "mttkrp": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mttkrp_noalloc": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mttkrp_nway": (i32, [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp), i64, i32, i32, vp, vp]),
+        "mtk_coo_create": (i32, [vp, ctypes.POINTER(i64), i64, P3, vp, vp, ctypes.POINTER(vp)]),
+        "mtk_coo_destroy": (i32, [vp]),
+        "mtk_coo_nnz": (i64, [vp]),
+        "mttkrp_coo": (i32, [vp, vp, P3, i64, i32, vp, vp]),
         "mttkrp_dimtree": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mtk_sweep_uses_dimtree": (i32, [ctypes.POINTER(i64), i64, i32]),
         "gram_solve": (i32, [vp, P3, ctypes.POINTER(i64), i64, i32, vp, vp, vp, vp]),
@@ -124,6 +133,21 @@ def _stream(stream=None) -> int:
 
 def _prec(p) -> int:
     return PREC_NAMES[p] if isinstance(p, str) else int(p)
+
+
+class CooTensor:
+    """An mtk_coo: a sparse tensor held on the device in the library's form."""
+
+    def __init__(self, L, h, dims, nnz):
+        self._L, self.h, self.dims, self.nnz = L, h, tuple(dims), nnz
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.mtk_coo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 class Context:
@@ -228,6 +252,28 @@ class Context:
         fp = (ctypes.c_void_p * n)(*[_ptr(f) for f in factors])
         self._chk(self._L.mttkrp_nway(self.h, _ptr(X), n, dims, fp, R, int(mode), _prec(prec), _ptr(out),
                                       _stream(stream)))
+        return out
+
+    def coo_create(self, dims, idx, vals, stream=None):
+        """Sparse tensor from coordinates: idx = three device int32 tensors
+        (nnz each), vals = device float32 (nnz); returns a CooTensor."""
+        dims = [int(d) for d in dims]
+        nnz = int(vals.numel())
+        h = ctypes.c_void_p()
+        ip = (ctypes.c_void_p * 3)(*[_ptr(i) for i in idx])
+        self._chk(self._L.mtk_coo_create(self.h, _dims(dims), nnz, ip, _ptr(vals), _stream(stream), ctypes.byref(h)))
+        return CooTensor(self._L, h, dims, nnz)
+
+    def mttkrp_coo(self, t, factors, mode: int, out=None, R=None, stream=None):
+        """Mode-n MTTKRP of a CooTensor (FP32)."""
+        import torch
+        R = int(R if R is not None else next(f for f in factors if f is not None).shape[1])
+        if out is None:
+            rows = t.dims[mode] if 0 <= int(mode) < 3 else 1
+            dev = next(f for f in factors if f is not None).device
+            out = torch.empty((rows, R), dtype=torch.float32, device=dev)
+        fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
+        self._chk(self._L.mttkrp_coo(self.h, t.h, fp, R, int(mode), _ptr(out), _stream(stream)))
         return out
 
     def mttkrp_dimtree(self, X, factors, mode: int, prec="fp32", out=None, R=None, stream=None):

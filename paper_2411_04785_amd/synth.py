@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs for dense 3-way CP workloads.
+"""Seeded synthetic inputs for dense (and sparse) 3-way CP workloads.
 
 This module only *draws* inputs: Gaussian factor matrices, CP-structured
 tensors (a sum of R outer products plus Gaussian noise), log-uniform slice
@@ -33,6 +33,7 @@ STREAM_NOISE = 1     # additive Gaussian noise (one sub-stream per slice)
 STREAM_INIT = 2      # query / initial factors given to MTTKRP and CP-ALS
 STREAM_SCALES = 3    # per-slice magnitudes
 STREAM_REQUESTS = 4  # serving request stream
+STREAM_SPARSE = 5    # coordinates and values of sparse tensors
 
 
 @dataclass(frozen=True)
@@ -223,3 +224,38 @@ def request_tensor(req: Request, pool: NoisePool):
     if w.noise_var > 0.0:
         X += np.float32(math.sqrt(w.noise_var)) * pool.window(X.size, w.seed).reshape(X.shape)
     return np.ascontiguousarray(X, dtype=np.float32), init_factors(w)
+
+
+def coo(dims: Sequence[int], nnz: int, seed: int, skew: Optional[float] = None,
+        integer: bool = False) -> Tuple[List[np.ndarray], np.ndarray]:
+    """A sparse 3-way tensor in coordinates: three int32 index arrays and
+    float32 values, nnz entries (repeats allowed: they add).
+
+    Indices are uniform over each mode, except that with ``skew`` (a Zipf
+    exponent > 1) the mode-0 index follows a power law -- index rank q drawn
+    with probability ~ q^-skew, ranks above dims[0] folded back -- mapped
+    through a seeded permutation so that the heavy rows are scattered.
+    Values are N(0, 1); with ``integer`` they are integers in [-3, 3] (all
+    products and sums of such values and integer factors stay exact in
+    FP32 for moderate sizes)."""
+    idx = []
+    for m, d in enumerate(dims):
+        g = rng(seed, STREAM_SPARSE, m)
+        if m == 0 and skew is not None:
+            q = (g.zipf(skew, nnz) - 1) % int(d)
+            perm = g.permutation(int(d))
+            idx.append(perm[q].astype(np.int32))
+        else:
+            idx.append(g.integers(0, int(d), nnz, dtype=np.int32))
+    g = rng(seed, STREAM_SPARSE, 3)
+    if integer:
+        vals = g.integers(-3, 4, nnz).astype(np.float32)
+    else:
+        vals = g.standard_normal(nnz, dtype=np.float32)
+    return idx, vals
+
+
+def integer_factors(seed: int, dims: Sequence[int], R: int, lo: int = -4, hi: int = 4) -> List[np.ndarray]:
+    """Factor matrices with integer entries in [lo, hi] (float32)."""
+    return [rng(seed, STREAM_INIT, m).integers(lo, hi + 1, (int(d), R)).astype(np.float32)
+            for m, d in enumerate(dims)]
