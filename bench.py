@@ -22,14 +22,15 @@ runs on the host cores as ``cpu_baseline`` (timed on a bounded sample); its
 full MTTKRPs also give each path's per-mode error over every output row.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
-                    [--workload cp1024_r64|cp512_r32|cp768_r128_sliced|cp64_r8|serve|copy]
+                    [--workload cp1024_r64|cp512_r32|cp768_r128_sliced|cp64_r8|serve|copy|
+                                coo64k_nnz64m_r64|coo64k_nnz64m_r64_zipf]
                     [--prec fp32|bf16x3|fp8] [--compare fp32|none] [--no-cpu-baseline]
 
 ``--workload cp768_r128_sliced`` (FP8 e4m3, per-slice scales) also runs the
 workload's 20 CP-ALS sweeps and reports their fit and model against the
 oracle's 20 sweeps (``tests/golden/cp768_r128_als.json``, written by the
 oracle).  ``--workload serve`` runs the serving workload instead (see
-serve_bench).
+serve_bench); the ``coo*`` workloads run sparse CP-ALS (see sparse_bench).
 """
 
 from __future__ import annotations
@@ -311,6 +312,110 @@ def copy_bench(args):
 
 
 
+SPARSE_WORKLOADS = {
+    # dims, nnz, R, Zipf exponent of the mode-0 index (None: uniform)
+    "coo64k_nnz64m_r64": ((1 << 16,) * 3, 1 << 26, 64, None),
+    "coo64k_nnz64m_r64_zipf": ((1 << 16,) * 3, 1 << 26, 64, 1.2),
+}
+
+
+def coo_bytes(dims, nnz, R, mode):
+    """Bytes a mode-n sparse MTTKRP must move: the entries in the library's
+    form (16 bytes each), the two gathered factors once, the output once."""
+    others = [d for m, d in enumerate(dims) if m != mode]
+    return 16 * nnz + 4 * R * sum(others) + 4 * R * dims[mode]
+
+
+def sparse_bench(args):
+    """Sparse CP-ALS on one MI355X: a step is one sweep (mttkrp_coo and
+    gram_solve for modes 0, 1, 2) over a seeded sparse tensor already in the
+    library's form on the device."""
+    import torch
+    import oracle
+    from paper_2411_04785_amd import synth
+    from paper_2411_04785_amd.mttkrp import Context
+    dims, nnz, R, skew = SPARSE_WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    idx, vals = synth.coo(dims, nnz, seed=2411, skew=skew)
+    facs = synth.gaussian_factors(2412, synth.STREAM_INIT, dims, R)
+    log(f"[bench] {args.workload}: inputs drawn in {time.perf_counter() - t0:.1f} s")
+    ctx = Context(0)
+    stream = torch.cuda.current_stream()
+    di = [torch.from_numpy(i).cuda() for i in idx]
+    dv = torch.from_numpy(vals).cuda()
+    f0 = [torch.from_numpy(f.astype(np.float32)).cuda() for f in facs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = ctx.coo_create(dims, di, dv)
+    create_s = time.perf_counter() - t0
+    del di, dv
+    mode_ms, outs = [], []
+    for mode in range(3):
+        out = ctx.mttkrp_coo(t, f0, mode)
+        mode_ms.append(time_calls(torch, stream, lambda: ctx.mttkrp_coo(t, f0, mode, out=out), args.mode_reps))
+        outs.append(out.cpu().numpy().astype(np.float64))
+        log(f"[bench] mode {mode}: {mode_ms[-1] * 1e3:.1f} us per sparse MTTKRP")
+    # Sampled output rows of every mode against the oracle over their entries.
+    g = np.random.default_rng(5)
+    worst = 0.0
+    for mode in range(3):
+        rows = np.unique(g.integers(0, dims[mode], 32))
+        sel = np.isin(idx[mode], rows)
+        sub = [i[sel] for i in idx]
+        ref = oracle.mttkrp_coo(sub, vals[sel], dims, facs, mode)[rows]
+        s_abs = oracle.mttkrp_coo(sub, np.abs(vals[sel]), dims, [np.abs(f) for f in facs], mode)[rows]
+        n = np.bincount(sub[mode], minlength=dims[mode])[rows].astype(np.float64)
+        bound = (n[:, None] + 3.0) * 2.0 ** -24 * s_abs
+        worst = max(worst, float((np.abs(outs[mode][rows] - ref) / np.maximum(bound, 1e-300)).max()))
+    fd = [f.clone() for f in f0]
+    lam = torch.ones(R, dtype=torch.float64, device="cuda")
+    ctx.als_sweep_coo(t, fd, lam, max(1, args.warmup))
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, stream)
+    e0.record(stream)
+    ctx.als_sweep_coo(t, fd, lam, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    flop_mttkrp = 3.0 * nnz * R
+    value = 3 * flop_mttkrp / (ms_step * 1e-3) / 1e9
+    m = int(np.argmax(mode_ms))
+    nbytes = coo_bytes(dims, nnz, R, m)
+    ach = nbytes / (mode_ms[m] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"mode-{m + 1} sparse MTTKRP (coo_mttkrp_kernel + zero fill + carry levels)",
+            "avg_launch_us": round(mode_ms[m] * 1e3, 2), "algorithmic_bytes": int(nbytes),
+            "factor_row_gather_bytes": int(8 * R * nnz),
+            "factor_row_gather_GBs": round(8 * R * nnz / (mode_ms[m] * 1e-3) / 1e9, 1)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        ns = 1 << 22
+        sub = [i[:ns] for i in idx]
+        ts = []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            oracle.mttkrp_coo(sub, vals[:ns], dims, facs, 0)
+            ts.append(time.perf_counter() - c0)
+        med = float(np.median(ts))
+        cpu = {"value": round(3.0 * ns * R / med / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 oracle mode-1 sparse MTTKRP (numpy gather + unbuffered scatter-add) of the first "
+                         f"{ns} entries of the same tensor, R={R}, median of 3 runs: "
+                         f"{', '.join(f'{x:.2f}' for x in ts)} s"}
+    print(json.dumps({
+        "metric": "sparse MTTKRP GFLOP/s (algorithmic, 3 x 3*nnz*R per sparse CP-ALS sweep)",
+        "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "dims": list(dims), "nnz": nnz, "R": R,
+                   "mode0_index": "uniform" if skew is None else f"zipf {skew}"},
+        "roofline": roof, "cpu_baseline": cpu,
+        "detail": {"mode_us": [round(x * 1e3, 1) for x in mode_ms], "create_s": round(create_s, 4),
+                   "sampled_rows_max_err_over_fp32_sum_bound": round(worst, 4),
+                   "lambda_finite": bool(torch.isfinite(lam).all().item())}}), flush=True)
+    t.close()
+
+
 def _events(torch, stream):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -464,6 +569,9 @@ def main():
         return
     if args.workload == "copy":
         copy_bench(args)
+        return
+    if args.workload in SPARSE_WORKLOADS:
+        sparse_bench(args)
         return
 
     import torch

@@ -216,6 +216,15 @@ int64_t mtk_coo_nnz(const mtk_coo* t);
 mtk_status mttkrp_coo(mtk_ctx* ctx, const mtk_coo* t, const float* const factors[3], int64_t R, int mode,
                       float* out, void* stream);
 
+/* CP-ALS sweeps on a sparse tensor: for modes 0, 1, 2 in order, mttkrp_coo
+ * into factors[mode] and gram_solve in place (the dense sweep's update,
+ * unchanged).  lambda (device FP64[R]) is overwritten; the factors given
+ * are the starting point.  Synchronises `stream` at the end and returns the
+ * sticky status (MTK_OK or MTK_ENOTSPD, see mtk_check).  MTK_EUNSUPPORTED
+ * if a dimension exceeds 2^30 (the update's limit). */
+mtk_status als_sweep_coo(mtk_ctx* ctx, const mtk_coo* t, float* const factors[3], double* lambda, int64_t R,
+                         int nsweeps, void* stream);
+
 /* Mode-0 or mode-1 MTTKRP by the dimension tree, the form als_sweep uses
  * for those two updates when mtk_sweep_uses_dimtree says so.  First
  * Y = X x_3 C, Y(i,j,r) = sum_k X(i,j,k) C(k,r) (an I*J x R FP32
@@ -248,7 +257,9 @@ int mtk_sweep_uses_dimtree(const int64_t dims[3], int64_t R, int prec);
  *  lambda_out[r] = ||F(:,r)||_2 (FP64); factor_out = F(:,r)/lambda_r cast
  *  to FP32 (a column with lambda_r == 0 is written unscaled).
  *  factors    : three device pointers (factors[mode] not read, may be NULL).
- *  dims, R    : as for mttkrp.
+ *  dims       : host int64[3], each in [1, 2^30] (no limit on the product:
+ *               the update never touches the tensor).
+ *  R          : 1..128.
  *  M          : device FP32 dims[mode] x R (an MTTKRP result).
  *  factor_out : device FP32 dims[mode] x R; may alias factors[mode] or M.
  *  lambda_out : device FP64[R].

@@ -62,9 +62,12 @@ void retire_graphs(mtk_ctx* c) {
   gc->execs.clear();
 }
 
+bool factor_dims_ok(const int64_t d[3]) {
+  return d[0] >= 1 && d[1] >= 1 && d[2] >= 1 && d[0] <= (1 << 30) && d[1] <= (1 << 30) && d[2] <= (1 << 30);
+}
+
 bool dims_ok(const int64_t d[3]) {
-  if (d[0] < 1 || d[1] < 1 || d[2] < 1) return false;
-  if (d[0] > (1 << 30) || d[1] > (1 << 30) || d[2] > (1 << 30)) return false;
+  if (!factor_dims_ok(d)) return false;
   const double n = (double)d[0] * d[1] * d[2];
   return n < 1099511627776.0;   // 2^40
 }
@@ -460,7 +463,7 @@ mtk_status gram_solve(mtk_ctx* c, const float* const factors[3], const int64_t d
                       const float* M, float* factor_out, double* lambda_out, void* stream) {
   if (!c) return MTK_EINVAL;
   if (!factors || !dims || !M || !factor_out || !lambda_out) return fail(c, MTK_EINVAL, "NULL argument");
-  if (!dims_ok(dims)) return fail(c, MTK_EINVAL, "dims out of range");
+  if (!factor_dims_ok(dims)) return fail(c, MTK_EINVAL, "dims out of range (each in [1, 2^30])");
   if (mode < 0 || mode > 2) return fail(c, MTK_EINVAL, "mode must be 0, 1 or 2");
   if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
   for (int m = 0; m < 3; ++m)

@@ -598,4 +598,25 @@ mtk_status mttkrp_coo(mtk_ctx* c, const mtk_coo* t, const float* const factors[3
   return MTK_OK;
 }
 
+mtk_status als_sweep_coo(mtk_ctx* c, const mtk_coo* t, float* const factors[3], double* lambda, int64_t R,
+                         int nsweeps, void* stream) {
+  if (!c) return MTK_EINVAL;
+  if (!t || !factors || !factors[0] || !factors[1] || !factors[2] || !lambda)
+    return coo_fail(c, MTK_EINVAL, "NULL argument");
+  if (nsweeps < 0) return coo_fail(c, MTK_EINVAL, "nsweeps must be >= 0");
+  if (R < 1 || R > mtk::kMaxRank) return coo_fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  for (int m = 0; m < 3; ++m)
+    if (t->dims[m] > (1 << 30)) return coo_fail(c, MTK_EUNSUPPORTED, "als_sweep_coo: a dimension exceeds 2^30");
+  const float* const cf[3] = {factors[0], factors[1], factors[2]};
+  for (int s = 0; s < nsweeps; ++s)
+    for (int mode = 0; mode < 3; ++mode) {
+      // The mode's MTTKRP goes straight into its factor (which it does not
+      // read), and the update overwrites it in place.
+      mtk_status st = mttkrp_coo(c, t, cf, R, mode, factors[mode], stream);
+      if (st == MTK_OK) st = gram_solve(c, cf, t->dims, R, mode, factors[mode], factors[mode], lambda, stream);
+      if (st != MTK_OK) return st;
+    }
+  return mtk_check(c, stream);
+}
+
 }  // extern "C"

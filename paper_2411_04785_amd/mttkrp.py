@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "MTK_OK", -1: "MTK_EINVAL", -2: "MTK_ENOMEM", -3: "MTK_EHIP",
                 -5: "MTK_EUNSUPPORTED", -6: "MTK_EBUDGET", -7: "MTK_EAGAIN"}
 
 EXPORTED = ["mtk_create", "mtk_destroy", "mtk_last_error", "mtk_check", "mtk_reserve",
-            "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_nway", "mtk_coo_create", "mtk_coo_destroy", "mtk_coo_nnz", "mttkrp_coo",
+            "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_nway", "mtk_coo_create", "mtk_coo_destroy", "mtk_coo_nnz", "mttkrp_coo", "als_sweep_coo",
             "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
             "als_sweep", "als_run", "mtk_graph_reset",
             "mtk_server_create", "mtk_server_submit", "mtk_server_poll", "mtk_server_stats",
@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
         "mtk_coo_destroy": (i32, [vp]),
         "mtk_coo_nnz": (i64, [vp]),
         "mttkrp_coo": (i32, [vp, vp, P3, i64, i32, vp, vp]),
+        "als_sweep_coo": (i32, [vp, vp, P3, vp, i64, i32, vp]),
         "mttkrp_dimtree": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mtk_sweep_uses_dimtree": (i32, [ctypes.POINTER(i64), i64, i32]),
         "gram_solve": (i32, [vp, P3, ctypes.POINTER(i64), i64, i32, vp, vp, vp, vp]),
@@ -275,6 +276,13 @@ class Context:
         fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
         self._chk(self._L.mttkrp_coo(self.h, t.h, fp, R, int(mode), _ptr(out), _stream(stream)))
         return out
+
+    def als_sweep_coo(self, t, factors, lam, nsweeps: int, stream=None):
+        """CP-ALS sweeps on a CooTensor, factors (float32) and lam (float64)
+        updated in place."""
+        R = int(factors[0].shape[1])
+        fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
+        self._chk(self._L.als_sweep_coo(self.h, t.h, fp, _ptr(lam), R, int(nsweeps), _stream(stream)))
 
     def mttkrp_dimtree(self, X, factors, mode: int, prec="fp32", out=None, R=None, stream=None):
         """Mode-0 / mode-1 MTTKRP through Y = X x3 C (the sweep's dimension tree)."""

@@ -181,3 +181,31 @@ def test_large_sampled_rows(ctx):
         ref = oracle.mttkrp_coo(sub, vals[sel], dims, facs, mode)[rows]
         b = _bound(sub, vals[sel], dims, facs, mode)[rows]
         assert (np.abs(got[rows] - ref) <= b).all(), mode
+
+
+def test_sparse_cp_als_matches_oracle(ctx):
+    # Entries observed at random positions of a rank-6 CP tensor (repeats
+    # add); five sparse CP-ALS sweeps on the device against the oracle's
+    # CP-ALS on the densified tensor from the same start.
+    import torch
+    dims, R = (40, 50, 60), 6
+    Xfull, _, init = synth.small_cp(dims, R, seed=17, noise_var=1e-4)
+    idx, _ = synth.coo(dims, 30000, seed=18)
+    vals = Xfull[idx[0], idx[1], idx[2]].astype(np.float32)
+    Xs = np.zeros(dims)
+    np.add.at(Xs, tuple(idx), vals.astype(np.float64))
+    of, ol, ofits = oracle.cp_als(Xs, init, 5)
+    di, dv, df = _dev(idx, vals, init)
+    t = ctx.coo_create(dims, di, dv)
+    lam = torch.ones(R, dtype=torch.float64, device="cuda")
+    ctx.als_sweep_coo(t, df, lam, 5)
+    t.close()
+    gf = [f.cpu().numpy() for f in df]
+    gl = lam.cpu().numpy()
+    gfit = oracle.fit(Xs, gf, gl)
+    model = oracle.reconstruct_slices(gf, gl, 0, dims[0])
+    ref = oracle.reconstruct_slices(of, ol, 0, dims[0])
+    me = float(np.linalg.norm(model - ref) / np.linalg.norm(ref))
+    _say(f"fit {gfit:.9f} oracle {ofits[-1]:.9f} model {me:.2e}")
+    assert abs(gfit - ofits[-1]) <= 1e-4
+    assert me <= 1e-3
