@@ -70,26 +70,51 @@ def algorithmic_bytes(dims, R, mode, prec):
     return b
 
 
+# The dense contraction kernels that a traffic record can describe are built
+# from these sources and the headers they include.
+DENSE_KERNEL_SOURCES = ("mttkrp_kernels.hip", "dimtree.hip")
+
+
+def kernel_source_files():
+    """DENSE_KERNEL_SOURCES and, transitively, the library headers they
+    include (the public header excepted: it declares, it builds nothing)."""
+    import re
+    d = os.path.join(ROOT, "paper_2411_04785_amd", "csrc")
+    seen, todo = set(), list(DENSE_KERNEL_SOURCES)
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(os.path.join(d, f)):
+            continue
+        seen.add(f)
+        todo += re.findall(r'^#include "([A-Za-z0-9_]+\.h)"', open(os.path.join(d, f)).read(), flags=re.M)
+    return sorted(seen)
+
+
 def kernel_sources_hash():
-    """sha256 prefix of the library's kernel sources (to tell whether a
-    recorded counter measurement still describes the built kernels)."""
+    """sha256 prefix of the dense contraction kernels' sources (to tell
+    whether a recorded counter measurement still describes the built
+    kernels)."""
     import hashlib
     d = os.path.join(ROOT, "paper_2411_04785_amd", "csrc")
-    names = sorted(f for f in os.listdir(d) if f.endswith((".hip", ".h")))
-    src = b"".join(open(os.path.join(d, f), "rb").read() for f in names)
+    src = b"".join(open(os.path.join(d, f), "rb").read() for f in kernel_source_files())
     return hashlib.sha256(src).hexdigest()[:16]
 
 
 def recorded_traffic(workload, prec, kernel=None):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
-    WRITE_SIZE runs, or None if none match this workload or the kernel
-    sources changed since."""
+    WRITE_SIZE runs, or None if none match this workload and kernel or the
+    kernel sources changed since.  A record holds either one kernel
+    ("kernel", "traffic_bytes_per_launch_mean") or several
+    ("traffic_bytes_per_launch": {kernel: bytes})."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_sources_sha256_16") != kernel_sources_hash():
         return None
+    per = rec.get("traffic_bytes_per_launch")
+    if per is not None:
+        return per.get(kernel) if kernel is not None else None
     if kernel is not None and rec.get("kernel", kernel) != kernel:
         return None
     return rec["traffic_bytes_per_launch_mean"]

@@ -43,3 +43,21 @@ def test_more_than_one_gpu_exits_with_message():
                        capture_output=True, text=True, timeout=600)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_kernel_source_files_cover_the_dense_kernels_only():
+    files = bench.kernel_source_files()
+    assert "mttkrp_kernels.hip" in files and "dimtree.hip" in files and "tile_device.h" in files
+    assert not {"sparse.hip", "server.hip", "als_kernels.hip", "api.hip"} & set(files)
+
+
+def test_recorded_traffic_per_kernel(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    rec = {"workload": "w", "prec": "fp8", "kernel_sources_sha256_16": "abcd" * 4,
+           "traffic_bytes_per_launch": {"k1": 10.0, "k2": 20.0}}
+    (tmp_path / "profiles" / "traffic_w_fp8.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_sources_hash", lambda: "abcd" * 4)
+    assert bench.recorded_traffic("w", "fp8", "k2") == 20.0
+    assert bench.recorded_traffic("w", "fp8", "k3") is None
+    assert bench.recorded_traffic("w", "fp8") is None
