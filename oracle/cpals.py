@@ -112,3 +112,47 @@ def cp_als(X: np.ndarray, init: Sequence[np.ndarray], sweeps: int,
         if fit_every_sweep and not record_mode_fits:
             fits.append(fit(X, factors, lam))
     return factors, lam, fits
+
+
+def cp_als_extrapolated(X: np.ndarray, init: Sequence[np.ndarray], sweeps: int, start: int = 2,
+                        step: Optional[float] = None):
+    """CP-ALS with an extrapolation step after every sweep s >= start
+    (sweeps counted from 1), in FP64.
+
+    After sweep s has produced A_s, B_s, C_s from the factors A_p, B_p it
+    started with, a candidate moves the first two factors further along
+    their last change,
+        A_E = normalise(A_p + d (A_s - A_p)),  B_E = normalise(B_p + d (B_s - B_p)),
+    with d = s^(1/3) (or the fixed ``step``), and solves the third factor
+    exactly from them: C_E, lambda_E = the mode-3 update from A_E and B_E.
+    The candidate replaces the sweep's result when its fit (explicit
+    residual) is higher.
+
+    Returns (factors, lambda, fits, accepted, cand_fits): fits[s] is the fit
+    kept after sweep s, accepted[s] whether the candidate was kept, and
+    cand_fits[s] the candidate's fit (None before ``start``).
+    """
+    factors: List[np.ndarray] = [np.asarray(f, dtype=np.float64).copy() for f in init]
+    lam = np.ones(factors[0].shape[1])
+    fits: List[float] = []
+    accepted: List[bool] = []
+    cand_fits: List[Optional[float]] = []
+    for s in range(1, sweeps + 1):
+        A_p, B_p = factors[0].copy(), factors[1].copy()
+        for n in range(3):
+            factors[n], lam = gram_solve(factors, mttkrp(X, factors, n), n)
+        f = fit(X, factors, lam)
+        took, fc = False, None
+        if s >= start:
+            d = float(step) if step is not None else s ** (1.0 / 3.0)
+            A_E, _ = normalize_columns(A_p + d * (factors[0] - A_p))
+            B_E, _ = normalize_columns(B_p + d * (factors[1] - B_p))
+            cand = [A_E, B_E, factors[2]]
+            cand[2], lam_E = gram_solve(cand, mttkrp(X, cand, 2), 2)
+            fc = fit(X, cand, lam_E)
+            if fc > f:
+                factors, lam, f, took = cand, lam_E, fc, True
+        fits.append(f)
+        accepted.append(took)
+        cand_fits.append(fc)
+    return factors, lam, fits, accepted, cand_fits

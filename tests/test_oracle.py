@@ -498,3 +498,72 @@ def test_pins_catch_coo_factor_swap():
     out = np.zeros((6, 3))
     np.add.at(out, idx[0], bad)
     assert rel(out, oracle.mttkrp_brute(X, facs, 0)) > 1e-3         # crossed indices are caught
+
+
+# ------------------------------------------------- CP-ALS with extrapolation ---
+
+def _swamp(dims, R, corr, seed, noise=0.01):
+    """A rank-R CP tensor whose factor columns share a common direction with
+    correlation `corr` in every mode (a 'swamp': plain ALS crawls), plus noise."""
+    g = np.random.default_rng(seed)
+    facs = []
+    for d in dims:
+        base = g.standard_normal(d)
+        facs.append(np.stack([corr * base + np.sqrt(1 - corr ** 2) * g.standard_normal(d) for _ in range(R)], 1))
+    X = np.einsum("ir,jr,kr->ijk", *facs)
+    X += noise * np.linalg.norm(X) / np.sqrt(X.size) * g.standard_normal(X.shape)
+    return X, [g.standard_normal((d, R)) for d in dims]
+
+
+def test_extrapolation_off_is_plain_als():
+    X, init = _swamp((12, 10, 9), 3, 0.8, 0)
+    f0, l0, fits0 = oracle.cp_als(X, init, 6)
+    f1, l1, fits1, acc, cand = oracle.cp_als_extrapolated(X, init, 6, start=7)
+    assert fits0 == fits1 and not any(acc) and all(c is None for c in cand)
+    assert all(np.array_equal(a, b) for a, b in zip(f0, f1)) and np.array_equal(l0, l1)
+
+
+def test_extrapolation_unit_step_reproduces_the_sweep():
+    # d = 1: A_E, B_E are the sweep's own (unit-column) factors, so the
+    # candidate's third factor is the sweep's and its fit the sweep's.
+    X, init = _swamp((12, 10, 9), 3, 0.9, 1)
+    _, _, fits0 = oracle.cp_als(X, init, 8)
+    _, _, fits1, acc, cand = oracle.cp_als_extrapolated(X, init, 8, start=2, step=1.0)
+    assert all(abs(c - f) < 1e-12 for c, f in zip(cand[1:], fits0[1:]))
+    assert np.allclose(fits1, fits0, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("corr,seed", [(0.0, 3), (0.9, 2)])
+def test_extrapolation_fits_never_decrease(corr, seed):
+    X, init = _swamp((14, 12, 10), 3, corr, seed)
+    _, _, fits, acc, cand = oracle.cp_als_extrapolated(X, init, 40)
+    assert all(b >= a - 1e-12 for a, b in zip(fits, fits[1:]))
+    assert all(f >= c for f, c in zip(fits, cand) if c is not None)   # the kept fit is the better one
+
+
+def _sweeps_to(fits, target):
+    return next((i + 1 for i, f in enumerate(fits) if f >= target), 10 ** 6)
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_extrapolation_cuts_sweeps_in_a_swamp(seed):
+    # Plain ALS on a collinear problem needs 50-110 sweeps to come within
+    # 1e-4 of its 150-sweep fit; with extrapolation from sweep 2 on (d =
+    # s^(1/3)) the same fit comes in at most 0.6 as many (measured 0.44-0.5).
+    X, init = _swamp((20, 18, 16), 3, 0.9, seed)
+    _, _, plain = oracle.cp_als(X, init, 150)
+    target = plain[-1] - 1e-4
+    _, _, ext, acc, _ = oracle.cp_als_extrapolated(X, init, 150)
+    n0, n1 = _sweeps_to(plain, target), _sweeps_to(ext, target)
+    assert n1 <= 0.6 * n0, (n0, n1)
+    assert sum(acc) > 10
+
+
+def test_pins_catch_a_backward_extrapolation():
+    # Stepping back along the last change (d = -1) is a plausible sign slip:
+    # its candidates are almost never better, and the swamp pin fails.
+    X, init = _swamp((20, 18, 16), 3, 0.9, 0)
+    _, _, plain = oracle.cp_als(X, init, 150)
+    target = plain[-1] - 1e-4
+    _, _, ext, acc, _ = oracle.cp_als_extrapolated(X, init, 150, step=-1.0)
+    assert _sweeps_to(ext, target) > 0.6 * _sweeps_to(plain, target)
