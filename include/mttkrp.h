@@ -311,6 +311,25 @@ mtk_status als_run(mtk_ctx* ctx, const mtk_tensor* X, float* const factors[3], d
                    int64_t R, int prec, int max_sweeps, double tol, double* fits_host,
                    int* sweeps_done, double* fit_final, void* stream);
 
+/* als_run with an extrapolation step after every sweep s >= ls_start
+ * (sweeps of this call counted from 1; ls_start >= 1).  After sweep s has
+ * taken the first two factors from A_p, B_p to A_s, B_s, a candidate moves
+ * them further along that change,
+ *     A_E = normalise(A_p + d (A_s - A_p)),  B_E = normalise(B_p + d (B_s - B_p)),
+ * d = s^(1/3), and solves the third factor exactly from A_E and B_E (one
+ * more mode-2 MTTKRP and update).  The candidate replaces the sweep's
+ * factors and lambda when its fit (from <F, M>, as for the per-sweep fit)
+ * is higher.  The standard line search by extrapolation for CP-ALS (the
+ * paper has no passage on it); a swamp of nearly collinear components is
+ * where it pays.  Each sweep from ls_start on costs one more pass over X.
+ *  fits_host     : NULL or host double[max_sweeps]: the fit kept after each sweep.
+ *  accepted_host : NULL or host int[max_sweeps]: 1 where the candidate was kept.
+ * Other arguments and the return value as for als_run. */
+mtk_status als_run_extrapolated(mtk_ctx* ctx, const mtk_tensor* X, float* const factors[3], double* lambda,
+                                int64_t R, int prec, int max_sweeps, double tol, int ls_start,
+                                double* fits_host, int* accepted_host, int* sweeps_done, double* fit_final,
+                                void* stream);
+
 /* Drop every cached als_sweep graph of this context and free the workspace
  * blocks it outgrew (a growing workspace keeps its old block, and the
  * graphs that use it, alive rather than wait for the device; they are

@@ -324,6 +324,34 @@ __global__ __launch_bounds__(256) void normalize_gram_kernel(const double* __res
   normalize_gram_body(F, n, R, colsq, nblk, status, lam, out, part, ipsum, ip, blockIdx.x, blockIdx.y);
 }
 
+// Extrapolation candidate of one factor: E = P + d (Q - P) in FP64 into the
+// solve region's F, with the per-16-row column sums of squares in the
+// layout apply_kernel leaves them (normalize_gram_kernel then gives the
+// unit-column FP32 factor, its norms and its Gram partials).  Workgroup
+// (row block, 16-column tile); each column's 16 squares are added in row order.
+__global__ __launch_bounds__(256) void extrapolate_kernel(const float* __restrict__ P, const float* __restrict__ Q,
+                                                          int64_t n, int R, double d, double* __restrict__ F,
+                                                          double* __restrict__ colsq) {
+  __shared__ double sq[kApplyRows][17];
+  const int rr = threadIdx.x >> 4, cc = threadIdx.x & 15;
+  const int64_t i = (int64_t)blockIdx.x * kApplyRows + rr;
+  const int c = blockIdx.y * 16 + cc;
+  double e = 0.0;
+  if (i < n && c < R) {
+    const double p = P[i * R + c], q = Q[i * R + c];
+    e = p + d * (q - p);
+    F[i * R + c] = e;
+  }
+  sq[rr][cc] = e * e;
+  __syncthreads();
+  if (rr == 0 && c < R) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kApplyRows; ++k) t += sq[k][cc];
+    colsq[(int64_t)blockIdx.x * R + c] = t;
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -485,6 +513,18 @@ hipError_t launch_apply(const int64_t dims[3], int R, int mode, const MSlices& m
   hipLaunchKernelGGL(normalize_gram_kernel, dim3(gram_pairs(R), gram_blocks(n, R)), dim3(256), 0, st, w.F, n, R, w.colsq,
                      nblk, status, lambda, factor_out, w.part[mode], with_ip ? w.ipsum : nullptr,
                      with_ip ? w.ip : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_extrapolate(const int64_t dims[3], int R, int mode, const float* P, const float* Q, double d,
+                              float* factor_out, double* lambda, int64_t maxdim, void* ws, int* status,
+                              hipStream_t st) {
+  const int64_t n = dims[mode];
+  SolveWs w = solve_ws(maxdim, R, ws);
+  const int nblk = (int)cdiv(n, kApplyRows);
+  hipLaunchKernelGGL(extrapolate_kernel, dim3(nblk, (R + 15) / 16), dim3(256), 0, st, P, Q, n, R, d, w.F, w.colsq);
+  hipLaunchKernelGGL(normalize_gram_kernel, dim3(gram_pairs(R), gram_blocks(n, R)), dim3(256), 0, st, w.F, n, R, w.colsq,
+                     nblk, status, lambda, factor_out, w.part[mode], nullptr, nullptr);
   return hipGetLastError();
 }
 

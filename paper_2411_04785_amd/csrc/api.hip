@@ -11,6 +11,15 @@
 #include <tuple>
 #include <vector>
 
+namespace mtk {
+// Extrapolation candidate of factor `mode` (als_kernels.hip): normalise(P +
+// d (Q - P)) into factor_out (FP32, unit columns; the norms into lambda) and
+// its Gram partials into the mode's slot of the solve region `ws`.
+hipError_t launch_extrapolate(const int64_t dims[3], int R, int mode, const float* P, const float* Q, double d,
+                              float* factor_out, double* lambda, int64_t maxdim, void* ws, int* status,
+                              hipStream_t st);
+}  // namespace mtk
+
 namespace {
 
 using mtk::ContractPlan;
@@ -673,8 +682,45 @@ mtk_status als_sweep(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], d
   return s;
 }
 
-mtk_status als_run(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int64_t R, int prec,
-                   int max_sweeps, double tol, double* fits_host, int* sweeps_done, double* fit_final, void* stream) {
+// Region of the extrapolation candidate, after the sweep's scratch: the
+// first two factors as a sweep found them, the candidate's three factors,
+// its lambda (and a discarded one), and a solve region of its own.
+struct LsRegion {
+  float* prev[2];
+  float* cand[3];
+  double* lam;
+  double* lam_discard;
+  void* solve;
+};
+
+static size_t ls_region_bytes(const int64_t dims[3], int R) {
+  const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
+  size_t b = 0;
+  for (int m = 0; m < 2; ++m) b += 2 * round256((size_t)dims[m] * R * sizeof(float));
+  b += round256((size_t)dims[2] * R * sizeof(float)) + 2 * round256((size_t)R * sizeof(double));
+  return b + mtk::solve_ws_bytes(maxdim, R);
+}
+
+static LsRegion ls_region(char* p, const int64_t dims[3], int R) {
+  LsRegion r{};
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += round256(bytes);
+    return q;
+  };
+  for (int m = 0; m < 2; ++m) r.prev[m] = reinterpret_cast<float*>(take((size_t)dims[m] * R * sizeof(float)));
+  for (int m = 0; m < 3; ++m) r.cand[m] = reinterpret_cast<float*>(take((size_t)dims[m] * R * sizeof(float)));
+  r.lam = reinterpret_cast<double*>(take((size_t)R * sizeof(double)));
+  r.lam_discard = reinterpret_cast<double*>(take((size_t)R * sizeof(double)));
+  r.solve = p;
+  return r;
+}
+
+// CP-ALS until the fit settles, optionally with an extrapolation candidate
+// after every sweep s >= ls_start (ls_start <= 0: none).
+static mtk_status als_run_impl(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int64_t R,
+                               int prec, int max_sweeps, double tol, int ls_start, double* fits_host,
+                               int* accepted_host, int* sweeps_done, double* fit_final, void* stream) {
   if (!c) return MTK_EINVAL;
   mtk_status s = check_tensor(c, X);
   if (s != MTK_OK) return s;
@@ -687,48 +733,110 @@ mtk_status als_run(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], dou
   *sweeps_done = 0;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int64_t maxdim = std::max(X->dims[0], std::max(X->dims[1], X->dims[2]));
-  const size_t need = round256((size_t)maxdim * R * sizeof(float)) + sweep_scratch_bytes(X->dims, (int)R, prec);
+  const int64_t* dims = X->dims;
+  const int64_t maxdim = std::max(dims[0], std::max(dims[1], dims[2]));
+  const size_t m_bytes = round256((size_t)maxdim * R * sizeof(float));
+  const size_t sweep_b = sweep_scratch_bytes(dims, (int)R, prec);
+  const bool ls = ls_start > 0 && max_sweeps >= ls_start;
+  const size_t need = m_bytes + sweep_b + (ls ? ls_region_bytes(dims, (int)R) : 0);
   if ((s = ensure_ws(c, need, st)) != MTK_OK) return s;
-  void* cws = static_cast<char*>(c->ws) + round256((size_t)maxdim * R * sizeof(float));
+  float* M = static_cast<float*>(c->ws);
+  void* cws = static_cast<char*>(c->ws) + m_bytes;
   const float* cf[3] = {factors[0], factors[1], factors[2]};
   if (max_sweeps > 0) {
     hipGraphExec_t exec = nullptr;
     if ((s = sweep_graph(c, X, factors, lambda, (int)R, prec, false, &exec)) != MTK_OK) return s;
     double acc[2] = {0.0, 0.0};
-    hipError_t e = mtk::launch_sumsq(X->data, X->fmt, X->slice_exp, X->dims, c->d_fit, cws, st);
+    hipError_t e = mtk::launch_sumsq(X->data, X->fmt, X->slice_exp, dims, c->d_fit, cws, st);
     if (e != hipSuccess) return hip_fail(c, e, "norm launch");
     HIP_OR_FAIL(c, hipMemcpyAsync(acc, c->d_fit, sizeof(acc), hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(c, hipStreamSynchronize(st));   // acc is host memory written by the copy
     if ((s = enqueue_initial_grams(c, X, factors, (int)R, prec, st)) != MTK_OK) return s;
-    const double* ip_dev = mtk::solve_ip(maxdim, (int)R, sweep_solve_ws(c, X->dims, (int)R, prec));
+    void* live_solve = sweep_solve_ws(c, dims, (int)R, prec);
+    const double* ip_dev = mtk::solve_ip(maxdim, (int)R, live_solve);
+    const LsRegion lr = ls ? ls_region(static_cast<char*>(cws) + sweep_b, dims, (int)R) : LsRegion{};
+    const double* cand_ip_dev = ls ? mtk::solve_ip(maxdim, (int)R, lr.solve) : nullptr;
     const double nx2 = acc[1];
+    auto fit_of = [&](double ip) { return 1.0 - std::sqrt(std::max(0.0, nx2 - ip)) / std::sqrt(nx2); };
     double prev = 0.0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
+      const int sweep_no = sw + 1;
+      const bool try_ls = ls && sweep_no >= ls_start;
+      if (try_ls)
+        for (int m = 0; m < 2; ++m)
+          HIP_OR_FAIL(c, hipMemcpyAsync(lr.prev[m], factors[m], (size_t)dims[m] * R * sizeof(float),
+                                        hipMemcpyDeviceToDevice, st));
       HIP_OR_FAIL(c, hipGraphLaunch(exec, st));
       double ip = 0.0;
       int status = 0;
       HIP_OR_FAIL(c, hipMemcpyAsync(&ip, ip_dev, sizeof(ip), hipMemcpyDeviceToHost, st));
       HIP_OR_FAIL(c, hipMemcpyAsync(&status, c->d_status, sizeof(status), hipMemcpyDeviceToHost, st));
       HIP_OR_FAIL(c, hipStreamSynchronize(st));
-      *sweeps_done = sw + 1;
+      *sweeps_done = sweep_no;
       if (status != 0) break;                    // reported by mtk_check below
       // At the least-squares solution of the last update, ||Xhat||^2 = <X, Xhat> = <F, M>.
-      const double fit = 1.0 - std::sqrt(std::max(0.0, nx2 - ip)) / std::sqrt(nx2);
+      double fit = fit_of(ip);
+      int took = 0;
+      if (try_ls) {
+        // Candidate: the first two factors moved further along their change
+        // over this sweep, the third solved exactly from them.
+        const double d = std::cbrt((double)sweep_no);
+        for (int m = 0; m < 2; ++m) {
+          e = mtk::launch_extrapolate(dims, (int)R, m, lr.prev[m], factors[m], d, lr.cand[m], lr.lam_discard, maxdim,
+                                      lr.solve, c->d_status, st);
+          if (e != hipSuccess) return hip_fail(c, e, "extrapolation launch");
+        }
+        const float* ef[3] = {lr.cand[0], lr.cand[1], factors[2]};
+        if ((s = mttkrp_impl(c, X, ef, (int)R, 2, prec, M, cws, st)) != MTK_OK) return s;
+        e = mtk::launch_update(dims, (int)R, 2, M, lr.cand[2], lr.lam, maxdim, lr.solve, c->d_status, st, true);
+        if (e != hipSuccess) return hip_fail(c, e, "extrapolation update launch");
+        double cip = 0.0;
+        HIP_OR_FAIL(c, hipMemcpyAsync(&cip, cand_ip_dev, sizeof(cip), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(c, hipMemcpyAsync(&status, c->d_status, sizeof(status), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(c, hipStreamSynchronize(st));
+        if (status != 0) break;
+        const double cfit = fit_of(cip);
+        if (cfit > fit) {
+          for (int m = 0; m < 3; ++m)
+            HIP_OR_FAIL(c, hipMemcpyAsync(factors[m], lr.cand[m], (size_t)dims[m] * R * sizeof(float),
+                                          hipMemcpyDeviceToDevice, st));
+          HIP_OR_FAIL(c, hipMemcpyAsync(lambda, lr.lam, (size_t)R * sizeof(double), hipMemcpyDeviceToDevice, st));
+          // The next sweep's first update reads the Gram matrices of the
+          // second and third factors from the live solve region.
+          if ((s = enqueue_initial_grams(c, X, factors, (int)R, prec, st)) != MTK_OK) return s;
+          fit = cfit;
+          took = 1;
+        }
+      }
       if (fits_host) fits_host[sw] = fit;
+      if (accepted_host) accepted_host[sw] = took;
       if (sw > 0 && std::fabs(fit - prev) < tol) break;
       prev = fit;
     }
   }
   if (fit_final) {
     double acc[2] = {0.0, 0.0};
-    hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, X->dims, cf, lambda, (int)R, c->d_fit, cws, st);
+    hipError_t e = mtk::launch_fit(X->data, X->fmt, X->slice_exp, dims, cf, lambda, (int)R, c->d_fit, cws, st);
     if (e != hipSuccess) return hip_fail(c, e, "fit launch");
     HIP_OR_FAIL(c, hipMemcpyAsync(acc, c->d_fit, sizeof(acc), hipMemcpyDeviceToHost, st));
     HIP_OR_FAIL(c, hipStreamSynchronize(st));
     *fit_final = 1.0 - std::sqrt(acc[0]) / std::sqrt(acc[1]);
   }
   return mtk_check(c, stream);
+}
+
+mtk_status als_run(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int64_t R, int prec,
+                   int max_sweeps, double tol, double* fits_host, int* sweeps_done, double* fit_final, void* stream) {
+  return als_run_impl(c, X, factors, lambda, R, prec, max_sweeps, tol, 0, fits_host, nullptr, sweeps_done, fit_final,
+                      stream);
+}
+
+mtk_status als_run_extrapolated(mtk_ctx* c, const mtk_tensor* X, float* const factors[3], double* lambda, int64_t R,
+                                int prec, int max_sweeps, double tol, int ls_start, double* fits_host,
+                                int* accepted_host, int* sweeps_done, double* fit_final, void* stream) {
+  if (c && ls_start < 1) return fail(c, MTK_EINVAL, "ls_start must be >= 1");
+  return als_run_impl(c, X, factors, lambda, R, prec, max_sweeps, tol, ls_start, fits_host, accepted_host,
+                      sweeps_done, fit_final, stream);
 }
 
 }  // extern "C"

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "MTK_OK", -1: "MTK_EINVAL", -2: "MTK_ENOMEM", -3: "MTK_EHIP",
 EXPORTED = ["mtk_create", "mtk_destroy", "mtk_last_error", "mtk_check", "mtk_reserve",
             "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_nway", "mtk_coo_create", "mtk_coo_destroy", "mtk_coo_nnz", "mttkrp_coo", "als_sweep_coo",
             "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
-            "als_sweep", "als_run", "mtk_graph_reset",
+            "als_sweep", "als_run", "als_run_extrapolated", "mtk_graph_reset",
             "mtk_server_create", "mtk_server_submit", "mtk_server_poll", "mtk_server_stats",
             "mtk_server_request_bytes", "mtk_server_destroy"]
 
@@ -99,6 +99,9 @@ def lib() -> ctypes.CDLL:
         "als_sweep": (i32, [vp, ctypes.POINTER(Tensor), P3, vp, i64, i32, i32, ctypes.POINTER(d), vp]),
         "als_run": (i32, [vp, ctypes.POINTER(Tensor), P3, vp, i64, i32, i32, d, ctypes.POINTER(d),
                           ctypes.POINTER(i32), ctypes.POINTER(d), vp]),
+        "als_run_extrapolated": (i32, [vp, ctypes.POINTER(Tensor), P3, vp, i64, i32, i32, d, i32,
+                                       ctypes.POINTER(d), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                       ctypes.POINTER(d), vp]),
         "mtk_graph_reset": (i32, [vp]),
         "mtk_server_create": (i32, [ctypes.POINTER(vp), i32, ctypes.c_uint64, i32]),
         "mtk_server_submit": (i32, [vp, i64, vp, ctypes.POINTER(i64), i64, i32, i32, P3, P3, vp]),
@@ -347,6 +350,24 @@ class Context:
                                   int(max_sweeps), float(tol), fits.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   ctypes.byref(done), ctypes.byref(ff) if final_fit else None, _stream(stream)))
         return fits[:done.value], done.value, (ff.value if final_fit else None)
+
+    def als_run_extrapolated(self, X, factors, lam, max_sweeps: int, ls_start: int = 2, prec="fp32",
+                             tol: float = 0.0, slice_exp=None, final_fit=True, stream=None, X_t=None):
+        """als_run with an extrapolation candidate after every sweep >=
+        ls_start.  Returns (per-sweep kept fits, accepted flags, sweeps run,
+        direct fit of the final model or None)."""
+        d = self.tensor_desc(X, slice_exp, X_t=X_t)
+        fp = (ctypes.c_void_p * 3)(*[_ptr(f) for f in factors])
+        fits = np.zeros(max(1, max_sweeps))
+        acc = np.zeros(max(1, max_sweeps), dtype=np.int32)
+        done = ctypes.c_int(0)
+        ff = ctypes.c_double(float("nan"))
+        self._chk(self._L.als_run_extrapolated(
+            self.h, ctypes.byref(d), fp, _ptr(lam), int(factors[0].shape[1]), _prec(prec), int(max_sweeps),
+            float(tol), int(ls_start), fits.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(done),
+            ctypes.byref(ff) if final_fit else None, _stream(stream)))
+        return fits[:done.value], acc[:done.value].astype(bool), done.value, (ff.value if final_fit else None)
 
     def graph_reset(self):
         self._chk(self._L.mtk_graph_reset(self.h))
