@@ -752,6 +752,8 @@ hipError_t dispatch_nt(const KArgs& a, const ContractPlan& p, hipStream_t st) {
     if (p.cm) {
       if (p.ntw == 1) return launch_cm<PREC, 1>(a, p, st);
       if (p.ntw == 2) return launch_cm<PREC, 2>(a, p, st);
+      if (p.ntw == 3) return launch_cm<PREC, 3>(a, p, st);
+      if (p.ntw == 4) return launch_cm<PREC, 4>(a, p, st);
       return hipErrorInvalidValue;
     }
   }
@@ -791,6 +793,12 @@ constexpr int64_t kMaxGridX = 0x7fffffff;
 #define MTK_STAGE_FLOATS 8192
 #endif
 
+// Most 16-column tiles one wave of the mode-3 (row-interleaved) kernel
+// holds; wider ranks split their columns over the fewest waves of a
+// workgroup (each such wave streams the same X rows).
+#ifndef MTK_CM_NTW
+#define MTK_CM_NTW 4
+#endif
 // Most 16-column MFMA tiles one FP8 wave holds (its two-term fragment takes
 // 16 VGPRs per tile); waves of a workgroup split wider ranks.
 #ifndef MTK_FP8_NTW
@@ -954,7 +962,7 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
   // rows read with 16-byte vectors (needs 16-byte aligned rows: K % 4 == 0).
   if (mode == 2 && !transposed && prec != MTK_FP8_E4M3 && x_aligned16 && K % 4 == 0) {
     p.cm = true;
-    p.ncg = p.nt <= 2 ? 1 : (p.nt <= 4 ? 2 : 4);
+    p.ncg = (int)cdiv(p.nt, MTK_CM_NTW);
     p.ntw = (int)cdiv(p.nt, p.ncg);
     p.nv = 8;
     p.kw = 32;
