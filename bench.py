@@ -5,7 +5,9 @@ Default workload (N=1): the 1024 x 1024 x 1024 FP32 tensor (4 GiB), rank-64
 CP model plus N(0, 1e-3) noise, R = 64 factors iid N(0,1) (synthetic,
 seeded).  The headline path is the bf16x3 contraction (each FP32 operand
 split into bf16 hi + lo, three bf16 MFMA products, FP32 accumulation); the
-plain FP32 path (FP32 MFMA) is timed beside it on the same tensor.  One step
+plain FP32 path (FP32 MFMA) and the bf16x6 path (three bf16 terms per
+operand, six products: FP32-level error) are timed beside it on the same
+tensor.  One step
 = one CP-ALS sweep on the device: for each mode an MTTKRP (for FP32 tensors
 with K >= 8R the mode-1 and mode-2 MTTKRPs come from one shared contraction
 Y = X x3 C, the dimension tree, so the sweep reads X twice) followed by the
@@ -24,7 +26,7 @@ full MTTKRPs also give each path's per-mode error over every output row.
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
                     [--workload cp1024_r64|cp512_r32|cp768_r128_sliced|cp64_r8|serve|copy|
                                 coo64k_nnz64m_r64|coo64k_nnz64m_r64_zipf]
-                    [--prec fp32|bf16x3|fp8] [--compare fp32|none] [--no-cpu-baseline]
+                    [--prec fp32|bf16x3|bf16x6|fp8] [--compare fp32[,bf16x6]|none] [--no-cpu-baseline]
 
 ``--workload cp768_r128_sliced`` (FP8 e4m3, per-slice scales) also runs the
 workload's 20 CP-ALS sweeps and reports their fit and model against the
@@ -48,9 +50,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Dense MFMA peaks per path, in algorithmic flops: bf16x3 issues three bf16
-# MFMA products per product of the definition, FP8 two e4m3 ones.
+# MFMA products per product of the definition, bf16x6 six, FP8 two e4m3 ones.
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
-PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6 / 3.0, "fp8": 5033.2 / 2.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6 / 3.0, "bf16x6": 2516.6 / 6.0, "fp8": 5033.2 / 2.0}
 DEFAULT_PREC = {"cp64_r8": "fp32", "cp512_r32": "fp32", "cp1024_r64": "bf16x3", "cp768_r128_sliced": "fp8"}
 
 
@@ -574,7 +576,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cp1024_r64")
     ap.add_argument("--prec", default=None)
-    ap.add_argument("--compare", default=None, help="path timed beside the headline (default fp32; none)")
+    ap.add_argument("--compare", default=None,
+                    help="paths timed beside the headline, comma-separated (default fp32, plus bf16x6 when the "
+                         "headline is bf16x3; none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode-reps", type=int, default=20)
     ap.add_argument("--requests", type=int, default=2000)
@@ -605,9 +609,12 @@ def main():
 
     w = synth.WORKLOADS[args.workload]
     prec = args.prec or DEFAULT_PREC[w.name]
-    compare = args.compare or "fp32"
-    if compare in ("none", prec):
-        compare = None
+    if args.compare is None:
+        compares = ["fp32", "bf16x6"] if prec == "bf16x3" else ["fp32"]
+    else:
+        compares = [c for c in args.compare.split(",") if c and c != "none"]
+    compares = [c for c in compares if c != prec]
+    compare = ",".join(compares) or None
     I, J, K = w.dims
     R = w.R
     log(f"[bench] workload {w.name} dims={w.dims} R={R} prec={prec} compare={compare}: generating input")
@@ -640,8 +647,8 @@ def main():
     if prec == "fp8" and w.als_sweeps:
         fp8_als = fp8_als_vs_oracle(ctx, torch, w, X_head, kw, Xd, f0)
         log(f"[bench] FP8 CP-ALS vs oracle: {fp8_als}")
-    if compare:
-        runs[compare] = run_path(ctx, torch, stream, w, compare, Xd, {}, f0, args)
+    for cp in compares:
+        runs[cp] = run_path(ctx, torch, stream, w, cp, Xd, {}, f0, args)
     fit = ctx.fit(X_head, runs[prec]["factors"], runs[prec]["lam"], **kw)
 
     flop_mttkrp = 2.0 * I * J * K * R
@@ -674,16 +681,15 @@ def main():
         if refs is not None:
             d["err_rel_per_mode_all_rows"], d["err_rel_worst_row"] = err_rows(r["outs"], refs)
         detail[p] = d
-    if compare:
-        detail["sweep_speedup_vs_" + compare] = round(runs[compare]["ms_step"] / head["ms_step"], 3)
-        detail["mttkrp_speedup_vs_" + compare] = [round(a / b, 3) for a, b in
-                                                  zip(runs[compare]["mode_ms"], head["mode_ms"])]
+    for cp in compares:
+        detail["sweep_speedup_vs_" + cp] = round(runs[cp]["ms_step"] / head["ms_step"], 3)
+        detail["mttkrp_speedup_vs_" + cp] = [round(a / b, 3) for a, b in zip(runs[cp]["mode_ms"], head["mode_ms"])]
     if fp8_als is not None:
         detail["fp8_als_vs_oracle"] = fp8_als
     if cpu is not None:
         detail["oracle_full_mode_s"] = cpu.pop("all_modes_s")
 
-    dtype = {"fp32": "f32", "bf16x3": "bf16x3", "fp8": "e4m3"}[prec]
+    dtype = {"fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6", "fp8": "e4m3"}[prec]
     line = {
         "metric": "MTTKRP GFLOP/s (algorithmic, 3 x 2IJKR per CP-ALS sweep) and % roofline vs plain FP32 at stated err",
         "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

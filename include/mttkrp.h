@@ -61,12 +61,18 @@ typedef enum {
  *                 lo = bf16(x - hi); the product is hi*hi + hi*lo + lo*hi
  *                 on bf16 MFMA (the lo*lo term, below 2^-16 relative, is
  *                 dropped).
+ *  MTK_BF16X6   : each FP32 operand split into three bf16 terms hi = bf16(x),
+ *                 mid = bf16(x - hi), lo = bf16(x - hi - mid) (together the
+ *                 24 significand bits of x); the six products down to 2^-16
+ *                 relative (lo*hi, hi*lo, mid*mid, mid*hi, hi*mid, hi*hi) on
+ *                 bf16 MFMA; what is dropped is below 2^-24, so the error
+ *                 is that of FP32 accumulation.  FP32 tensors; not served.
  *  MTK_FP8_E4M3 : OCP e4m3 tensor with per mode-1 slice power-of-two scales
  *                 (see mtk_quantize_fp8) on e4m3 MFMA; the factor inside the
  *                 contraction is held as two e4m3 terms, hi = e4m3(g 2^-eh)
  *                 and lo = e4m3((g - hi 2^eh) 2^-el), with power-of-two
  *                 scales eh, el per column (about 2^-8 relative). */
-typedef enum { MTK_FP32 = 0, MTK_BF16X3 = 1, MTK_FP8_E4M3 = 2 } mtk_prec;
+typedef enum { MTK_FP32 = 0, MTK_BF16X3 = 1, MTK_FP8_E4M3 = 2, MTK_BF16X6 = 3 } mtk_prec;
 
 /* Dense tensor descriptor.
  *  data      : device pointer; FP32 values (fmt MTK_FP32) or e4m3 codes, one
@@ -126,7 +132,7 @@ mtk_status mtk_quantize_fp8(mtk_ctx* ctx, const float* x, const int64_t dims[3],
  *             dims[n] x R).  factors[mode] is not read and may be NULL.
  *  R        : 1 <= R <= 128.
  *  mode     : 0, 1 or 2.
- *  prec     : MTK_FP32 or MTK_BF16X3 for an FP32 tensor; MTK_FP8_E4M3 for
+ *  prec     : MTK_FP32, MTK_BF16X3 or MTK_BF16X6 for an FP32 tensor; MTK_FP8_E4M3 for
  *             an FP8 tensor (the tensor's fmt decides; prec must match).
  *  out      : device FP32, dims[mode] x R row-major; fully overwritten.
  * The result is deterministic: the summation order depends only on
@@ -168,7 +174,7 @@ mtk_status mttkrp_noalloc(mtk_ctx* ctx, const mtk_tensor* X, const float* const 
  *            group's product <= 2^30 (else MTK_EUNSUPPORTED).
  *  factors : host array of nmodes device pointers (dims[m] x R, FP32,
  *            row-major); factors[mode] is not read and may be NULL.
- *  prec    : MTK_FP32 or MTK_BF16X3.
+ *  prec    : MTK_FP32, MTK_BF16X3 or MTK_BF16X6.
  *  R, mode, out, stream : as for mttkrp (out is dims[mode] x R). */
 mtk_status mttkrp_nway(mtk_ctx* ctx, const float* X, int nmodes, const int64_t* dims,
                        const float* const* factors, int64_t R, int mode, int prec, float* out,
@@ -234,7 +240,7 @@ mtk_status als_sweep_coo(mtk_ctx* ctx, const mtk_coo* t, float* const factors[3]
  * which is the mttkrp result with its sums associated differently (equal up
  * to rounding).  Deterministic, and bitwise equal to the MTTKRP of the same
  * mode inside an als_sweep that uses the tree.
- *  X     : FP32 tensor, prec MTK_FP32 or MTK_BF16X3 (arithmetic of the
+ *  X     : FP32 tensor, prec MTK_FP32, MTK_BF16X3 or MTK_BF16X6 (arithmetic of the
  *          contraction with C; the sums over Y are FP32).
  *  mode  : 0 or 1.  factors[2] and factors[1 - mode] are read.
  *  R, out, stream : as for mttkrp.

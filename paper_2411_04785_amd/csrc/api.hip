@@ -121,7 +121,8 @@ mtk_status check_tensor(mtk_ctx* c, const mtk_tensor* X) {
 }
 
 mtk_status check_prec(mtk_ctx* c, const mtk_tensor* X, int prec) {
-  if (prec != MTK_FP32 && prec != MTK_BF16X3 && prec != MTK_FP8_E4M3) return fail(c, MTK_EINVAL, "unknown precision");
+  if (prec != MTK_FP32 && prec != MTK_BF16X3 && prec != MTK_BF16X6 && prec != MTK_FP8_E4M3)
+    return fail(c, MTK_EINVAL, "unknown precision");
   if (X->fmt == MTK_FP8_E4M3 && prec != MTK_FP8_E4M3) return fail(c, MTK_EINVAL, "FP8 tensor requires prec MTK_FP8_E4M3");
   if (X->fmt == MTK_FP32 && prec == MTK_FP8_E4M3) return fail(c, MTK_EINVAL, "prec MTK_FP8_E4M3 requires an FP8 tensor (mtk_quantize_fp8)");
   return MTK_OK;
@@ -403,7 +404,8 @@ mtk_status mttkrp_nway(mtk_ctx* c, const float* X, int nmodes, const int64_t* di
   if (nmodes < 3 || nmodes > mtk::kMaxNwayModes) return fail(c, MTK_EINVAL, "nmodes must be in [3, 8]");
   if (mode < 0 || mode >= nmodes) return fail(c, MTK_EINVAL, "mode out of range");
   if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
-  if (prec != MTK_FP32 && prec != MTK_BF16X3) return fail(c, MTK_EINVAL, "mttkrp_nway: prec must be MTK_FP32 or MTK_BF16X3");
+  if (prec != MTK_FP32 && prec != MTK_BF16X3 && prec != MTK_BF16X6)
+    return fail(c, MTK_EINVAL, "mttkrp_nway: prec must be MTK_FP32, MTK_BF16X3 or MTK_BF16X6");
   if (reinterpret_cast<uintptr_t>(X) & 3) return fail(c, MTK_EINVAL, "X not 4-byte aligned");
   double total = 1.0;
   for (int m = 0; m < nmodes; ++m) {
@@ -448,7 +450,7 @@ mtk_status mttkrp_dimtree(mtk_ctx* c, const mtk_tensor* X, const float* const fa
   mtk_status s = check_tensor(c, X);
   if (s != MTK_OK) return s;
   if ((s = check_prec(c, X, prec)) != MTK_OK) return s;
-  if (X->fmt != MTK_FP32) return fail(c, MTK_EINVAL, "mttkrp_dimtree takes an FP32 tensor (prec MTK_FP32 or MTK_BF16X3)");
+  if (X->fmt != MTK_FP32) return fail(c, MTK_EINVAL, "mttkrp_dimtree takes an FP32 tensor (prec MTK_FP32, MTK_BF16X3 or MTK_BF16X6)");
   if (mode != 0 && mode != 1) return fail(c, MTK_EINVAL, "mttkrp_dimtree: mode must be 0 or 1");
   if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
   if (!factors || !out || !factors[2] || !factors[1 - mode]) return fail(c, MTK_EINVAL, "NULL factors or out");

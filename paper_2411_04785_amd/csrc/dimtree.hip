@@ -158,12 +158,7 @@ __global__ __launch_bounds__(256) void ttm_kernel(TtmArgs a) {
             const float4 v = bc[2 * s + h4];
             const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              __bf16 h, l;
-              split_bf16(ok ? vv[e] : 0.f, h, l);
-              fr.hi[t][s][4 * h4 + e] = h;
-              fr.lo[t][s][4 * h4 + e] = l;
-            }
+            for (int e = 0; e < 4; ++e) frag_put(fr, t, s, 4 * h4 + e, ok ? vv[e] : 0.f);
           }
       }
     }
@@ -392,7 +387,8 @@ size_t dimtree_ws_bytes(const int64_t dims[3], int R) {
 hipError_t launch_dimtree_mttkrp(int mode, bool form_y, const float* X, bool x_aligned16, const int64_t dims[3],
                                  const float* const factors[3], int R, int prec, float* out, void* ws,
                                  hipStream_t st, const FactorArgs* job, MSlices* defer) {
-  if ((mode != 0 && mode != 1) || (prec != MTK_FP32 && prec != MTK_BF16X3) || R < 1 || R > kMaxRank)
+  if ((mode != 0 && mode != 1) || (prec != MTK_FP32 && prec != MTK_BF16X3 && prec != MTK_BF16X6) || R < 1 ||
+      R > kMaxRank)
     return hipErrorInvalidValue;
   if (job && job->R > kJobMaxRank) return hipErrorInvalidValue;
   const int64_t I = dims[0], J = dims[1], K = dims[2];
@@ -419,7 +415,9 @@ hipError_t launch_dimtree_mttkrp(int mode, bool form_y, const float* X, bool x_a
       t.I = I;
     }
     const bool vec = x_aligned16 && K % 4 == 0;
-    e = prec == MTK_FP32 ? launch_ttm_prec<MTK_FP32>(t, vec, st) : launch_ttm_prec<MTK_BF16X3>(t, vec, st);
+    e = prec == MTK_FP32     ? launch_ttm_prec<MTK_FP32>(t, vec, st)
+        : prec == MTK_BF16X3 ? launch_ttm_prec<MTK_BF16X3>(t, vec, st)
+                             : launch_ttm_prec<MTK_BF16X6>(t, vec, st);
     if (e != hipSuccess) return e;
     if (fused) {
       if (defer) {

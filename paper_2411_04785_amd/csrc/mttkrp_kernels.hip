@@ -45,7 +45,7 @@ namespace {
 struct KArgs {
   const void* X;
   const int32_t* slice_exp;   // FP8 tensor: per mode-1 slice exponent
-  const float* frag_src;      // fragment factor G, nRed x R (FP32 / BF16X3)
+  const float* frag_src;      // fragment factor G, nRed x R (FP32 / BF16X3 / BF16X6)
   const uint8_t* frag_q;      // FP8: e4m3 codes of G, column-major R x red_pad, hi then lo plane
   int red_pad;                // FP8: padded column length of frag_q (covers every window)
   const int32_t* frag_exp;    // FP8: per-column exponent of G
@@ -130,17 +130,14 @@ __device__ __forceinline__ void load_frag(Frag<PREC, NT, NV>& fr, const KArgs& a
         const int red = red0 + e;
         fr.f[t][e] = (col_ok && red < a.nRed) ? a.frag_src[(int64_t)red * a.R + col] : 0.f;
       }
-    } else if constexpr (PREC == MTK_BF16X3) {
+    } else if constexpr (PREC == MTK_BF16X3 || PREC == MTK_BF16X6) {
 #pragma unroll
       for (int s = 0; s < NV / 8; ++s) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int red = red0 + s * 8 + e;
-          float v = (col_ok && red < a.nRed) ? a.frag_src[(int64_t)red * a.R + col] : 0.f;
-          __bf16 h, l;
-          split_bf16(v, h, l);
-          fr.hi[t][s][e] = h;
-          fr.lo[t][s][e] = l;
+          const float v = (col_ok && red < a.nRed) ? a.frag_src[(int64_t)red * a.R + col] : 0.f;
+          frag_put(fr, t, s, e, v);
         }
       }
     } else {
@@ -373,23 +370,14 @@ __device__ __forceinline__ void tile_mfma_cm(f4 (&T)[4][NT], const XRegsCM<NV>& 
     for (int s = 0; s < NV / 8; ++s) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        bf16x8 ah, al;
+        float xs[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 h, l;
-          split_bf16(x.v[s * 8 + e][c], h, l);
-          ah[e] = h;
-          al[e] = l;
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) T[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, fr.hi[t][s], T[c][t], 0, 0, 0);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) T[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.lo[t][s], T[c][t], 0, 0, 0);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) T[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.hi[t][s], T[c][t], 0, 0, 0);
+        for (int e = 0; e < 8; ++e) xs[e] = x.v[s * 8 + e][c];
+        split_step<PREC, NT, NV>(T[c], xs, fr, s);
       }
     }
   }
+
 }
 
 template <int PREC, int NT, int NV>
@@ -793,6 +781,10 @@ constexpr int64_t kMaxGridX = 0x7fffffff;
 #define MTK_STAGE_FLOATS 8192
 #endif
 
+// Most fragment VGPRs per lane a bf16x6 plan gives a wave (sets its nv).
+#ifndef MTK_X6_FRAG_REGS
+#define MTK_X6_FRAG_REGS 96
+#endif
 // Most 16-column tiles one wave of the mode-3 (row-interleaved) kernel
 // holds; wider ranks split their columns over the fewest waves of a
 // workgroup (each such wave streams the same X rows).
@@ -870,8 +862,10 @@ struct Slots {
 Slots plan_slots(const ContractPlan& p, int prec) {
   static std::mutex mu;
   static std::map<std::pair<const void*, size_t>, Slots> cache;
-  const void* k = prec == MTK_FP32 ? kernel_of_prec<MTK_FP32>(p)
-                  : prec == MTK_BF16X3 ? kernel_of_prec<MTK_BF16X3>(p) : kernel_of_prec<MTK_FP8_E4M3>(p);
+  const void* k = prec == MTK_FP32     ? kernel_of_prec<MTK_FP32>(p)
+                  : prec == MTK_BF16X3 ? kernel_of_prec<MTK_BF16X3>(p)
+                  : prec == MTK_BF16X6 ? kernel_of_prec<MTK_BF16X6>(p)
+                                       : kernel_of_prec<MTK_FP8_E4M3>(p);
   // LDS at the largest loop block: staged weights plus the wave-sum area.
   const size_t red = p.cm ? (size_t)4 * 16 * p.ntw * 64 : (p.wr > 1 ? (size_t)4 * p.ntw * 4 * 64 : 0);
   const size_t lds = ((size_t)std::max(1, MTK_STAGE_FLOATS / p.R) * p.R + red) * sizeof(float);
@@ -962,7 +956,8 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
   // rows read with 16-byte vectors (needs 16-byte aligned rows: K % 4 == 0).
   if (mode == 2 && !transposed && prec != MTK_FP8_E4M3 && x_aligned16 && K % 4 == 0) {
     p.cm = true;
-    p.ncg = (int)cdiv(p.nt, MTK_CM_NTW);
+    // bf16x6's third fragment term leaves a four-tile wave one wave per SIMD.
+    p.ncg = (int)cdiv(p.nt, prec == MTK_BF16X6 ? 2 : MTK_CM_NTW);
     p.ntw = (int)cdiv(p.nt, p.ncg);
     p.nv = 8;
     p.kw = 32;
@@ -976,7 +971,8 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
     return p;
   }
 
-  // Fragment registers per lane: nt*nv (FP32, BF16X3 hi+lo) or nt*nv/4 (FP8); keep <= 64.
+  // Fragment registers per lane: nt*nv (FP32; BF16X3 hi+lo), 3 nt*nv/2
+  // (BF16X6 hi+mid+lo) or nt*nv/4 (FP8); keep <= 64 (BF16X6: MTK_X6_FRAG_REGS).
   int nv;
   if (prec == MTK_FP8_E4M3) {
     nv = 128;
@@ -984,7 +980,11 @@ ContractPlan make_plan(const int64_t dims[3], int R, int mode, int prec, bool x_
     while (nv > 32 && 4 * (nv / 2) >= p.nRed) nv /= 2;
   } else {
     nv = MTK_NV_MAX;
-    while (nv > 8 && p.ntw * nv > 64) nv /= 2;
+    if (prec == MTK_BF16X6) {
+      while (nv > 8 && 3 * p.ntw * nv / 2 > MTK_X6_FRAG_REGS) nv /= 2;
+    } else {
+      while (nv > 8 && p.ntw * nv > 64) nv /= 2;
+    }
     while (nv > 8 && 4 * (nv / 2) >= p.nRed) nv /= 2;
   }
   p.nv = nv;
@@ -1055,6 +1055,7 @@ hipError_t launch_contract(const ContractPlan& p, int prec, int mode, const void
   switch (prec) {
     case MTK_FP32: e = dispatch_nt<MTK_FP32>(a, p, st); break;
     case MTK_BF16X3: e = dispatch_nt<MTK_BF16X3>(a, p, st); break;
+    case MTK_BF16X6: e = dispatch_nt<MTK_BF16X6>(a, p, st); break;
     case MTK_FP8_E4M3: e = dispatch_nt<MTK_FP8_E4M3>(a, p, st); break;
     default: return hipErrorInvalidValue;
   }

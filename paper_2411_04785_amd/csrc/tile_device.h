@@ -24,12 +24,14 @@ __device__ __forceinline__ f4 zero4() { return f4{0.f, 0.f, 0.f, 0.f}; }
 template <int PREC> struct PrecT;
 template <> struct PrecT<MTK_FP32> { using XT = float; static constexpr int kStep = 1; };
 template <> struct PrecT<MTK_BF16X3> { using XT = float; static constexpr int kStep = 8; };
+template <> struct PrecT<MTK_BF16X6> { using XT = float; static constexpr int kStep = 8; };
 template <> struct PrecT<MTK_FP8_E4M3> { using XT = uint8_t; static constexpr int kStep = 32; };
 
 // X tile registers of one lane: nv reduction values of one row.
 template <int PREC, int NV> struct XRegs;
 template <int NV> struct XRegs<MTK_FP32, NV> { float v[NV]; };
 template <int NV> struct XRegs<MTK_BF16X3, NV> { float v[NV]; };
+template <int NV> struct XRegs<MTK_BF16X6, NV> { float v[NV]; };
 template <int NV> struct XRegs<MTK_FP8_E4M3, NV> { uint32_t w[NV / 4]; };
 
 // Load this lane's nv reduction values of tile row `m` (global offset `off`
@@ -116,12 +118,27 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = static_cast<__bf16>(x - static_cast<float>(hi));
 }
 
+// Three-term split: hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi -
+// mid); both differences are exact, and the three 8-bit significands cover
+// the 24 of a binary32 value (x = hi + mid + lo for normal values).
+__device__ __forceinline__ void split3_bf16(float x, __bf16& hi, __bf16& mid, __bf16& lo) {
+  hi = static_cast<__bf16>(x);
+  const float r = x - static_cast<float>(hi);
+  mid = static_cast<__bf16>(r);
+  lo = static_cast<__bf16>(r - static_cast<float>(mid));
+}
+
 // Fragment of the factor G held by one lane for the whole kernel: for N-tile
 // t and MFMA step s, the values G(red0 + s*kStep + e, t*16 + n) for the
 // lane's element slots e (n = lane & 15, red0 = window start + g*nv).
 template <int PREC, int NT, int NV> struct Frag;
 template <int NT, int NV> struct Frag<MTK_FP32, NT, NV> { float f[NT][NV]; };
 template <int NT, int NV> struct Frag<MTK_BF16X3, NT, NV> { bf16x8 hi[NT][NV / 8]; bf16x8 lo[NT][NV / 8]; };
+template <int NT, int NV> struct Frag<MTK_BF16X6, NT, NV> {
+  bf16x8 hi[NT][NV / 8];
+  bf16x8 mid[NT][NV / 8];
+  bf16x8 lo[NT][NV / 8];
+};
 // FP8: the factor is held as two e4m3 terms, hi = e4m3(G 2^-eh) and
 // lo = e4m3((G - hi 2^eh) 2^-el), with per-column exponents eh, el.  The
 // exponents of the lane's column travel as E8M0 B-operand scales (127 + e),
@@ -131,6 +148,72 @@ template <int NT, int NV> struct Frag<MTK_FP8_E4M3, NT, NV> {
   i32x8 ql[NT][NV / 32];
   int sh[NT], sl[NT];
 };
+
+// Factor value v into slot (t, s, e) of a split (bf16x3 / bf16x6) fragment.
+template <int PREC, int NT, int NV>
+__device__ __forceinline__ void frag_put(Frag<PREC, NT, NV>& fr, int t, int s, int e, float v) {
+  if constexpr (PREC == MTK_BF16X3) {
+    __bf16 h, l;
+    split_bf16(v, h, l);
+    fr.hi[t][s][e] = h;
+    fr.lo[t][s][e] = l;
+  } else if constexpr (PREC == MTK_BF16X6) {
+    __bf16 h, m, l;
+    split3_bf16(v, h, m, l);
+    fr.hi[t][s][e] = h;
+    fr.mid[t][s][e] = m;
+    fr.lo[t][s][e] = l;
+  }
+}
+
+// One bf16 MFMA step of a split path for every N-tile t: the 8 X values xs
+// of the lane (reduction slots of step s) split like the fragment, and the
+// products accumulated smallest first.  bf16x3: x_lo G_hi, x_hi G_lo,
+// x_hi G_hi (x_lo G_lo, below 2^-16 relative, dropped).  bf16x6: the six
+// products down to 2^-16 relative (x_lo G_hi, x_hi G_lo, x_mid G_mid, x_mid
+// G_hi, x_hi G_mid, x_hi G_hi); the dropped ones are below 2^-24.
+template <int PREC, int NT, int NV>
+__device__ __forceinline__ void split_step(f4 (&T)[NT], const float (&xs)[8], const Frag<PREC, NT, NV>& fr,
+                                           int s) {
+  if constexpr (PREC == MTK_BF16X3) {
+    bf16x8 ah, al;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 h, l;
+      split_bf16(xs[e], h, l);
+      ah[e] = h;
+      al[e] = l;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, fr.hi[t][s], T[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.lo[t][s], T[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.hi[t][s], T[t], 0, 0, 0);
+  } else {
+    bf16x8 ah, am, al;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 h, m, l;
+      split3_bf16(xs[e], h, m, l);
+      ah[e] = h;
+      am[e] = m;
+      al[e] = l;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, fr.hi[t][s], T[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.lo[t][s], T[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, fr.mid[t][s], T[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, fr.hi[t][s], T[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.mid[t][s], T[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.hi[t][s], T[t], 0, 0, 0);
+  }
+}
 
 // T[t] = X-tile (16 x kw) times fragment (kw x 16) for every N-tile t
 // (ACC: added to T[t] instead).
@@ -147,24 +230,13 @@ __device__ __forceinline__ void tile_mfma(f4 (&T)[NT], const XRegs<PREC, NV>& x,
 #pragma unroll
       for (int t = 0; t < NT; ++t)
         T[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.v[s], fr.f[t][s], T[t], 0, 0, 0);
-  } else if constexpr (PREC == MTK_BF16X3) {
+  } else if constexpr (PREC == MTK_BF16X3 || PREC == MTK_BF16X6) {
 #pragma unroll
     for (int s = 0; s < NV / 8; ++s) {
-      bf16x8 ah, al;
+      float xs[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        __bf16 h, l;
-        split_bf16(x.v[s * 8 + e], h, l);
-        ah[e] = h;
-        al[e] = l;
-      }
-      // Small cross terms first, then the leading hi*hi term.
-#pragma unroll
-      for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, fr.hi[t][s], T[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.lo[t][s], T[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) T[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, fr.hi[t][s], T[t], 0, 0, 0);
+      for (int e = 0; e < 8; ++e) xs[e] = x.v[s * 8 + e];
+      split_step<PREC, NT, NV>(T, xs, fr, s);
     }
   } else {
 #pragma unroll

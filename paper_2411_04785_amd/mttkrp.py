@@ -20,8 +20,8 @@ LIB_PATH = os.environ.get("MTK_LIBRARY") or os.path.join(_HERE, "libmttkrp.so")
 
 MTK_OK, MTK_EINVAL, MTK_ENOMEM, MTK_EHIP, MTK_ENOTSPD, MTK_EUNSUPPORTED, MTK_EBUDGET, MTK_EAGAIN = \
     0, -1, -2, -3, -4, -5, -6, -7
-FP32, BF16X3, FP8_E4M3 = 0, 1, 2
-PREC_NAMES = {"fp32": FP32, "bf16x3": BF16X3, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
+FP32, BF16X3, FP8_E4M3, BF16X6 = 0, 1, 2, 3
+PREC_NAMES = {"fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
 STATUS_NAMES = {0: "MTK_OK", -1: "MTK_EINVAL", -2: "MTK_ENOMEM", -3: "MTK_EHIP", -4: "MTK_ENOTSPD",
                 -5: "MTK_EUNSUPPORTED", -6: "MTK_EBUDGET", -7: "MTK_EAGAIN"}
 

@@ -84,7 +84,7 @@ def test_fit_matches_oracle(ctx):
     assert abs(got - oracle.fit(X, tf, np.ones(4))) <= 1e-9
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 def test_als_sweeps_match_oracle(ctx, prec):
     from gpu_util import dev, host, rel
     w, X, facs = _small(dims=(60, 50, 40), rank=5, R=5, noise=1e-4, seed=33)
@@ -154,7 +154,7 @@ def test_graph_replay_equals_eager(ctx, dims, R):
         assert np.array_equal(host(x), host(y))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("dims,R", [((70, 45, 200), 20), ((33, 40, 330), 40), ((12, 256, 160), 16),
                                     ((10, 512, 400), 40)])
 def test_dimtree_sweeps_match_oracle(ctx, prec, dims, R):
@@ -203,7 +203,7 @@ def test_als_run_fits_and_replay(ctx):
     assert abs(ffin - ofits[-1]) <= 1e-6
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 def test_als_run_stops_when_fit_settles(ctx, prec):
     from gpu_util import dev
     w, X, facs = _small(dims=(48, 40, 64), rank=4, R=4, noise=1e-3, seed=92)

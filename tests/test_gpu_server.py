@@ -172,3 +172,14 @@ def test_large_ranks_and_zero_sweeps():
     z, _ = _served([(7, X, init)], "fp32", 0, slots=1)
     assert z[7]["status"] == 0
     assert abs(z[7]["fit"] - oracle.fit(X, init, np.ones(init[0].shape[1]))) <= 1e-10
+
+
+def test_bf16x6_is_not_served():
+    # The grouped serving kernels are built for FP32 and bf16x3 requests.
+    from paper_2411_04785_amd.mttkrp import Server, MtkError, MTK_EINVAL
+    q, X, init = _reqs(1, seed=3)[0]
+    srv = Server(0, budget_bytes=10**9, max_slots=2)
+    with pytest.raises(MtkError) as ei:
+        srv.submit(q, X, init, "bf16x6", sweeps=1)
+    assert ei.value.status == MTK_EINVAL
+    srv.close()

@@ -35,7 +35,7 @@ def _case(dims, R, seed):
     return synth.tensor(w, threads=4), synth.init_factors(w)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6", "fp8"])
 def test_noalloc_matches_mttkrp_twice(ctx, prec):
     import torch
     from gpu_util import dev, host, rel
