@@ -34,7 +34,8 @@ that reduce to library routines, invariants and library casts -- in
 from .mttkrp import khatri_rao, unfold, mttkrp, mttkrp_rows, mttkrp_brute  # noqa: F401
 from .mttkrp import khatri_rao_many, unfold_nway, mttkrp_nway, mttkrp_nway_brute, mttkrp_coo  # noqa: F401
 from .cpals import (gram_hadamard, gram_solve, normalize_columns, cp_als, cp_als_extrapolated,  # noqa: F401
-                    reconstruct_slices, fit)
+                     gram_hadamard_nway, fit_nway, cp_als_nway,
+                     reconstruct_slices, fit)
 from .formats import (bf16_round, bf16x2_split, e4m3_values, e4m3_encode,  # noqa: F401
                       e4m3_decode, slice_scale_exponent, quantize_slices_e4m3,
                       dequantize_slices_e4m3)

@@ -156,3 +156,45 @@ def cp_als_extrapolated(X: np.ndarray, init: Sequence[np.ndarray], sweeps: int, 
         accepted.append(took)
         cand_fits.append(fc)
     return factors, lam, fits, accepted, cand_fits
+
+
+def gram_hadamard_nway(factors: Sequence[np.ndarray], mode: int) -> np.ndarray:
+    """V = elementwise product of A_m^T A_m over every mode m != mode (FP64),
+    for any number of factors."""
+    R = np.asarray(factors[0]).shape[1]
+    V = np.ones((R, R))
+    for m, F in enumerate(factors):
+        if m != mode:
+            F = np.asarray(F, dtype=np.float64)
+            V = V * (F.T @ F)
+    return V
+
+
+def fit_nway(X: np.ndarray, factors: Sequence[np.ndarray], lam: np.ndarray) -> float:
+    """fit = 1 - ||X - Xhat||_F / ||X||_F for an N-way CP model, Xhat formed
+    explicitly in FP64 through its mode-1 unfolding A_1 diag(lambda) (Khatri-
+    Rao product of the other factors)^T."""
+    from .mttkrp import khatri_rao_many
+    X = np.asarray(X, dtype=np.float64)
+    F = [np.asarray(f, dtype=np.float64) for f in factors]
+    Xh = (F[0] * np.asarray(lam, dtype=np.float64)) @ khatri_rao_many(F[1:]).T
+    return float(1.0 - np.linalg.norm(X.reshape(X.shape[0], -1) - Xh) / np.linalg.norm(X))
+
+
+def cp_als_nway(X: np.ndarray, init: Sequence[np.ndarray], sweeps: int):
+    """Fixed-count CP-ALS of an N-way tensor in FP64: each sweep updates the
+    factors in mode order, A_n = M_n V^{-1} with M_n the mode-n MTTKRP and V
+    the Hadamard product of the other factors' Gram matrices, then normalises
+    its columns (the norms become lambda).  ``init`` is used as given.
+    Returns (factors, lambda, fits) with fits[s] the fit after sweep s."""
+    from .mttkrp import mttkrp_nway
+    factors: List[np.ndarray] = [np.asarray(f, dtype=np.float64).copy() for f in init]
+    lam = np.ones(factors[0].shape[1])
+    fits: List[float] = []
+    for _ in range(sweeps):
+        for n in range(len(factors)):
+            M = mttkrp_nway(X, factors, n)
+            V = gram_hadamard_nway(factors, n)
+            factors[n], lam = normalize_columns(np.linalg.solve(V, M.T).T)
+        fits.append(fit_nway(X, factors, lam))
+    return factors, lam, fits

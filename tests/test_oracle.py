@@ -567,3 +567,61 @@ def test_pins_catch_a_backward_extrapolation():
     target = plain[-1] - 1e-4
     _, _, ext, acc, _ = oracle.cp_als_extrapolated(X, init, 150, step=-1.0)
     assert _sweeps_to(ext, target) > 0.6 * _sweeps_to(plain, target)
+
+
+# ------------------------------------------------------------ N-way CP-ALS ---
+
+def _cp_nway(dims, R, seed, noise=0.0):
+    g = np.random.default_rng(seed)
+    facs = [g.standard_normal((d, R)) for d in dims]
+    X = np.einsum(",".join(f"{chr(97 + m)}r" for m in range(len(dims))) + "->" +
+                  "".join(chr(97 + m) for m in range(len(dims))), *facs)
+    X = X + noise * np.linalg.norm(X) / np.sqrt(X.size) * g.standard_normal(X.shape)
+    return X, facs, [g.standard_normal((d, R)) for d in dims]
+
+
+def test_nway_als_at_three_ways_is_cp_als():
+    X, _, init = _cp_nway((9, 8, 7), 3, 1, noise=0.05)
+    f0, l0, fits0 = oracle.cp_als(X, init, 5)
+    f1, l1, fits1 = oracle.cp_als_nway(X, init, 5)
+    assert np.allclose(fits0, fits1, rtol=0, atol=1e-12)
+    assert all(np.allclose(a, b, rtol=0, atol=1e-10) for a, b in zip(f0, f1))
+
+
+def test_nway_fit_matches_brute_reconstruction():
+    g = np.random.default_rng(4)
+    dims, R = (3, 4, 2, 5), 2
+    X = g.standard_normal(dims)
+    F = [g.standard_normal((d, R)) for d in dims]
+    lam = np.array([0.7, -1.3])
+    Xh = np.zeros(dims)
+    for idx in np.ndindex(*dims):
+        Xh[idx] = sum(lam[r] * np.prod([F[m][idx[m], r] for m in range(4)]) for r in range(R))
+    assert abs(oracle.fit_nway(X, F, lam) - (1 - np.linalg.norm(X - Xh) / np.linalg.norm(X))) < 1e-13
+
+
+@pytest.mark.parametrize("dims,R,seed", [((6, 5, 4, 7), 3, 2), ((4, 3, 5, 3, 4), 2, 3)])
+def test_nway_als_recovers_an_exact_cp_tensor(dims, R, seed):
+    X, _, init = _cp_nway(dims, R, seed)
+    _, _, fits = oracle.cp_als_nway(X, init, 60)
+    assert fits[-1] > 1 - 1e-6
+    assert all(b >= a - 1e-12 for a, b in zip(fits, fits[1:]))
+
+
+def test_pins_catch_nway_gram_of_the_wrong_modes():
+    # Taking every Gram (the updated mode's too) into V is a plausible slip:
+    # the updates then stop solving the normal equations and the exact
+    # tensor is not recovered.
+    # (here the iteration even runs into a singular V).
+    X, _, init = _cp_nway((6, 5, 4, 7), 3, 2)
+    F = [np.asarray(f, np.float64).copy() for f in init]
+    try:
+        for _ in range(60):
+            for n in range(4):
+                M = oracle.mttkrp_nway(X, F, n)
+                V = oracle.gram_hadamard_nway(F, -1)
+                F[n], lam = oracle.normalize_columns(np.linalg.solve(V, M.T).T)
+        recovered = oracle.fit_nway(X, F, lam) > 1 - 1e-6
+    except np.linalg.LinAlgError:
+        recovered = False
+    assert not recovered
