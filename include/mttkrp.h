@@ -231,6 +231,24 @@ mtk_status mttkrp_coo(mtk_ctx* ctx, const mtk_coo* t, const float* const factors
 mtk_status als_sweep_coo(mtk_ctx* ctx, const mtk_coo* t, float* const factors[3], double* lambda, int64_t R,
                          int nsweeps, void* stream);
 
+/* CP-ALS sweeps of an N-way tensor (3 <= N <= 8): each sweep updates the
+ * factors in mode order, A_n = M_n V^{-1} with M_n the mode-n MTTKRP (as
+ * mttkrp_nway computes it) and V the Hadamard product of the Gram matrices
+ * of the other N-1 factors, then normalises A_n's columns into lambda.  In
+ * the three-way view of mode n the merged groups' factors are their
+ * Khatri-Rao products, whose Gram matrices are the Hadamard products of
+ * their factors' Grams, so each update is gram_solve on that view.  The
+ * standard CP-ALS (the paper has no passage on it).
+ *  X, nmodes, dims, R, prec : as for mttkrp_nway (every merged dimension
+ *          <= 2^30, else MTK_EUNSUPPORTED).
+ *  factors : host array of nmodes device pointers (dims[m] x R FP32), the
+ *            starting point, updated in place.
+ *  lambda  : device FP64[R], overwritten.
+ * Synchronises `stream` at the end and returns the sticky status (MTK_OK or
+ * MTK_ENOTSPD, see mtk_check). */
+mtk_status als_sweep_nway(mtk_ctx* ctx, const float* X, int nmodes, const int64_t* dims, float* const* factors,
+                          double* lambda, int64_t R, int prec, int nsweeps, void* stream);
+
 /* Mode-0 or mode-1 MTTKRP by the dimension tree, the form als_sweep uses
  * for those two updates when mtk_sweep_uses_dimtree says so.  First
  * Y = X x_3 C, Y(i,j,r) = sum_k X(i,j,k) C(k,r) (an I*J x R FP32

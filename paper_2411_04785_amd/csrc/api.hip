@@ -444,6 +444,80 @@ mtk_status mttkrp_nway(mtk_ctx* c, const float* X, int nmodes, const int64_t* di
   return mttkrp_impl(c, &t3, f3, (int)R, w.vm, prec, out, wp, st);
 }
 
+mtk_status als_sweep_nway(mtk_ctx* c, const float* X, int nmodes, const int64_t* dims, float* const* factors,
+                          double* lambda, int64_t R, int prec, int nsweeps, void* stream) {
+  if (!c) return MTK_EINVAL;
+  if (!X || !dims || !factors || !lambda) return fail(c, MTK_EINVAL, "NULL argument");
+  if (nmodes < 3 || nmodes > mtk::kMaxNwayModes) return fail(c, MTK_EINVAL, "nmodes must be in [3, 8]");
+  if (R < 1 || R > mtk::kMaxRank) return fail(c, MTK_EINVAL, "R must be in [1, 128]");
+  if (nsweeps < 0) return fail(c, MTK_EINVAL, "nsweeps must be >= 0");
+  if (prec != MTK_FP32 && prec != MTK_BF16X3 && prec != MTK_BF16X6)
+    return fail(c, MTK_EINVAL, "als_sweep_nway: prec must be MTK_FP32, MTK_BF16X3 or MTK_BF16X6");
+  if (reinterpret_cast<uintptr_t>(X) & 3) return fail(c, MTK_EINVAL, "X not 4-byte aligned");
+  double total = 1.0;
+  for (int m = 0; m < nmodes; ++m) {
+    if (dims[m] < 1 || dims[m] > (1 << 30)) return fail(c, MTK_EINVAL, "dims out of range");
+    if (!factors[m]) return fail(c, MTK_EINVAL, "NULL factor pointer");
+    total *= (double)dims[m];
+  }
+  if (total >= 1099511627776.0) return fail(c, MTK_EINVAL, "tensor has 2^40 elements or more");
+  // Workspace: [solve region][M][Khatri-Rao matrices of the two merged
+  // groups][contraction], each part sized for the largest over the modes.
+  size_t solve_b = 0, m_b = 0, kr_b = 0, con_b = 0;
+  for (int n = 0; n < nmodes; ++n) {
+    const NwayView w = nway_view(nmodes, dims, n);
+    for (int p = 0; p < 3; ++p)
+      if (w.v[p] > (1 << 30)) return fail(c, MTK_EUNSUPPORTED, "als_sweep_nway: a merged dimension exceeds 2^30");
+    const int64_t d3[3] = {w.v[0], w.v[1], w.v[2]};
+    solve_b = std::max(solve_b, mtk::solve_ws_bytes(std::max(d3[0], std::max(d3[1], d3[2])), (int)R));
+    m_b = std::max(m_b, round256((size_t)dims[n] * R * sizeof(float)));
+    size_t k = 0;
+    for (int p = 0; p < 3; ++p)
+      if (p != w.vm && w.hi[p] - w.lo[p] > 1) k += round256((size_t)w.v[p] * R * sizeof(float));
+    kr_b = std::max(kr_b, k);
+    con_b = std::max(con_b, mttkrp_ws(d3, (int)R, w.vm, prec));
+  }
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  mtk_status s = ensure_ws(c, round256(solve_b) + m_b + kr_b + con_b, st);
+  if (s != MTK_OK) return s;
+  char* solve_ws = static_cast<char*>(c->ws);
+  float* M = reinterpret_cast<float*>(solve_ws + round256(solve_b));
+  char* kr_ws = reinterpret_cast<char*>(M) + m_b;
+  void* cws = kr_ws + kr_b;
+  for (int sw = 0; sw < nsweeps; ++sw)
+    for (int n = 0; n < nmodes; ++n) {
+      // Mode n in the three-way view (P, d_n, Q): the merged groups' factors
+      // are their Khatri-Rao products, whose Gram matrices are the Hadamard
+      // products of their factors' Grams, so the three-way update is the
+      // N-way one.
+      const NwayView w = nway_view(nmodes, dims, n);
+      const int64_t d3[3] = {w.v[0], w.v[1], w.v[2]};
+      const mtk_tensor t3{X, nullptr, {d3[0], d3[1], d3[2]}, MTK_FP32, nullptr};
+      const float* f3[3] = {nullptr, nullptr, nullptr};
+      char* wp = kr_ws;
+      for (int p = 0; p < 3; ++p) {
+        if (p == w.vm) {
+          f3[p] = factors[n];
+          continue;
+        }
+        if (w.hi[p] - w.lo[p] == 1) {
+          f3[p] = factors[w.lo[p]];
+          continue;
+        }
+        float* kr = reinterpret_cast<float*>(wp);
+        wp += round256((size_t)w.v[p] * R * sizeof(float));
+        hipError_t e = mtk::launch_kr_rows(factors + w.lo[p], dims + w.lo[p], w.hi[p] - w.lo[p], (int)R, kr, st);
+        if (e != hipSuccess) return hip_fail(c, e, "Khatri-Rao launch");
+        f3[p] = kr;
+      }
+      if ((s = mttkrp_impl(c, &t3, f3, (int)R, w.vm, prec, M, cws, st)) != MTK_OK) return s;
+      hipError_t e = mtk::launch_gram_solve(f3, d3, (int)R, w.vm, M, factors[n], lambda, solve_ws, c->d_status, st);
+      if (e != hipSuccess) return hip_fail(c, e, "N-way update launch");
+    }
+  return mtk_check(c, stream);
+}
+
 mtk_status mttkrp_dimtree(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], int64_t R, int mode,
                           int prec, float* out, void* stream) {
   if (!c) return MTK_EINVAL;

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "MTK_OK", -1: "MTK_EINVAL", -2: "MTK_ENOMEM", -3: "MTK_EHIP",
                 -5: "MTK_EUNSUPPORTED", -6: "MTK_EBUDGET", -7: "MTK_EAGAIN"}
 
 EXPORTED = ["mtk_create", "mtk_destroy", "mtk_last_error", "mtk_check", "mtk_reserve",
-            "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_nway", "mtk_coo_create", "mtk_coo_destroy", "mtk_coo_nnz", "mttkrp_coo", "als_sweep_coo",
+            "mtk_quantize_fp8", "mttkrp", "mttkrp_noalloc", "mttkrp_nway", "als_sweep_nway", "mtk_coo_create", "mtk_coo_destroy", "mtk_coo_nnz", "mttkrp_coo", "als_sweep_coo",
             "mttkrp_dimtree", "mtk_sweep_uses_dimtree", "gram_solve", "mtk_fit",
             "als_sweep", "als_run", "als_run_extrapolated", "mtk_graph_reset",
             "mtk_server_create", "mtk_server_submit", "mtk_server_poll", "mtk_server_stats",
@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
         "mttkrp": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mttkrp_noalloc": (i32, [vp, ctypes.POINTER(Tensor), P3, i64, i32, i32, vp, vp]),
         "mttkrp_nway": (i32, [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp), i64, i32, i32, vp, vp]),
+        "als_sweep_nway": (i32, [vp, vp, i32, ctypes.POINTER(i64), ctypes.POINTER(vp), vp, i64, i32, i32, vp]),
         "mtk_coo_create": (i32, [vp, ctypes.POINTER(i64), i64, P3, vp, vp, ctypes.POINTER(vp)]),
         "mtk_coo_destroy": (i32, [vp]),
         "mtk_coo_nnz": (i64, [vp]),
@@ -257,6 +258,15 @@ class Context:
         self._chk(self._L.mttkrp_nway(self.h, _ptr(X), n, dims, fp, R, int(mode), _prec(prec), _ptr(out),
                                       _stream(stream)))
         return out
+
+    def als_sweep_nway(self, X, factors, lam, nsweeps: int, prec="fp32", stream=None):
+        """CP-ALS sweeps of an N-way FP32 tensor, factors (FP32) and lam (FP64)
+        updated in place."""
+        n = X.dim()
+        dims = (ctypes.c_int64 * n)(*[int(d) for d in X.shape])
+        fp = (ctypes.c_void_p * n)(*[_ptr(f) for f in factors])
+        self._chk(self._L.als_sweep_nway(self.h, _ptr(X), n, dims, fp, _ptr(lam), int(factors[0].shape[1]),
+                                         _prec(prec), int(nsweeps), _stream(stream)))
 
     def coo_create(self, dims, idx, vals, stream=None):
         """Sparse tensor from coordinates: idx = three device int32 tensors

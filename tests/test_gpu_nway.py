@@ -16,6 +16,11 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp32": 1e-5, "bf16x3": 1e-5}
 
 
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
 @pytest.fixture(scope="module")
 def ctx():
     import torch
@@ -123,3 +128,55 @@ def test_nway_argument_errors(ctx):
         ctx.mttkrp_nway(dev(X2), [dev(f) for f in f2], 0, "fp32")
     ok = ctx.mttkrp_nway(Xd, [None, fd[1], fd[2], fd[3]], 0, "fp32")     # factors[mode] may be NULL
     assert tuple(ok.shape) == (4, 4)
+
+
+def _cp_tensor(dims, rank, R, seed, noise):
+    g = np.random.default_rng(seed)
+    facs = [g.standard_normal((d, rank)) for d in dims]
+    letters = "abcdefgh"[:len(dims)]
+    X = np.einsum(",".join(c + "r" for c in letters) + "->" + letters, *facs)
+    X = X + noise * np.linalg.norm(X) / np.sqrt(X.size) * g.standard_normal(X.shape)
+    return X.astype(np.float32), [g.standard_normal((d, R)).astype(np.float32) for d in dims]
+
+
+def _model(facs, lam):
+    return (facs[0] * lam) @ oracle.khatri_rao_many(facs[1:]).T
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("dims,rank,R", [((30, 26, 24), 4, 4), ((20, 18, 16, 22), 5, 5), ((9, 8, 10, 7, 6), 4, 4),
+                                         ((6, 5, 7, 4, 5, 6), 3, 3)])
+def test_nway_sweeps_match_oracle(ctx, prec, dims, rank, R):
+    # Sweeps from the same start as the oracle's N-way CP-ALS: the kept model
+    # (through its mode-1 unfolding) and its explicit fit.
+    import torch
+    X, init = _cp_tensor(dims, rank, R, seed=len(dims) * 10 + R, noise=0.02)
+    Xd = torch.from_numpy(X).cuda()
+    fd = [torch.from_numpy(f.copy()).cuda() for f in init]
+    lam = torch.ones(R, dtype=torch.float64, device="cuda")
+    ctx.als_sweep_nway(Xd, fd, lam, 6, prec)
+    of, ol, ofits = oracle.cp_als_nway(X.astype(np.float64), init, 6)
+    gf = [f.cpu().numpy().astype(np.float64) for f in fd]
+    gl = lam.cpu().numpy()
+    gfit = oracle.fit_nway(X.astype(np.float64), gf, gl)
+    me = float(np.linalg.norm(_model(gf, gl) - _model(of, ol)) / np.linalg.norm(_model(of, ol)))
+    _say("als nway", dims, R, prec, f"fit {gfit:.9f} oracle {ofits[-1]:.9f} model {me:.2e}")
+    assert abs(gfit - ofits[-1]) <= (1e-5 if prec == "fp32" else 1e-4)
+    assert me <= (1e-4 if prec == "fp32" else 1e-3)
+
+
+def test_nway_sweeps_arguments(ctx):
+    import torch
+    from paper_2411_04785_amd.mttkrp import MtkError, MTK_EINVAL
+    X, init = _cp_tensor((5, 4, 3, 6), 2, 2, seed=1, noise=0.0)
+    Xd = torch.from_numpy(X).cuda()
+    fd = [torch.from_numpy(f.copy()).cuda() for f in init]
+    lam = torch.ones(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(MtkError) as ei:
+        ctx.als_sweep_nway(Xd, fd, lam, -1)
+    assert ei.value.status == MTK_EINVAL
+    with pytest.raises(MtkError) as ei:
+        ctx.als_sweep_nway(Xd, fd, lam, 1, "fp8")
+    assert ei.value.status == MTK_EINVAL
+    ctx.als_sweep_nway(Xd, fd, lam, 0)           # no sweep: factors unchanged
+    assert all(np.array_equal(f.cpu().numpy(), g) for f, g in zip(fd, init))
