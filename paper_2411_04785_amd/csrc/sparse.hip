@@ -9,7 +9,13 @@
 // sorted by their mode-n index (stable: entries with equal index keep the
 // input order), each entry 16 bytes {row, a, b, value} where row is the
 // mode-n index and a, b the indices of the two other modes in increasing
-// mode order.  The sort is an LSD radix sort on 8-bit digits written here
+// mode order.  Where a gathered factor is too large for one XCD's L2, the
+// mode is partitioned: the entries are first ordered by which of 8 equal
+// index ranges of that factor they fall in (part; of the two gathered
+// factors the one that spreads the entries more evenly), rows ascending
+// within each part,
+// part p is walked by workgroups of XCD p, each part writes its own partial
+// output, and the partials are added in part order.  The sort is an LSD radix sort on 8-bit digits written here
 // (histogram per 4096-entry tile, exclusive scan, stable scatter with
 // per-wave ballot ranking).
 //
@@ -43,6 +49,7 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 entries per tile
 constexpr int kScanTile = 4096;                       // elements per scan block
 constexpr int kCooMaxSeg = 1024;                      // longest segment (entries)
+constexpr int kCooParts = 8;                          // parts of a partitioned mode (one per XCD)
 
 // ----------------------------------------------------------- preparation ---
 
@@ -206,6 +213,31 @@ __global__ __launch_bounds__(256) void coo_gather_kernel(const int32_t* __restri
   }
 }
 
+
+// Part of each entry for a partitioned mode: which of `parts` equal ranges
+// of the first gathered factor's rows its index a falls in.
+__global__ __launch_bounds__(256) void coo_part_key_kernel(const int32_t* __restrict__ perm,
+                                                           const int32_t* __restrict__ ia, int64_t da, int parts,
+                                                           int64_t nnz, int32_t* __restrict__ key) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = perm ? perm[p] : p;
+    key[p] = (int32_t)((int64_t)ia[o] * parts / da);
+  }
+}
+
+// Entries per part if the parts are the equal index ranges of ia
+// (integer counts: order does not matter).
+__global__ __launch_bounds__(256) void coo_part_count_kernel(const int32_t* __restrict__ ia, int64_t da, int parts,
+                                                             int64_t nnz, int* __restrict__ cnt) {
+  __shared__ int c[kCooParts];
+  if (threadIdx.x < kCooParts) c[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&c[(int64_t)ia[p] * parts / da], 1);
+  __syncthreads();
+  if (threadIdx.x < kCooParts && c[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], c[threadIdx.x]);
+}
+
 // ----------------------------------------------------------- contraction ---
 
 template <int RL, int T>
@@ -219,19 +251,36 @@ __device__ __forceinline__ void store_row(float* __restrict__ dst, const float (
 
 constexpr int kCooUnroll = 4;
 
+// Segments of one mode: part p holds entries [ent[p], ent[p+1]) and
+// segments [seg[p], seg[p+1]) of the global segment numbering (carry slots).
+struct CooSegs {
+  int64_t ent[kCooParts + 1];
+  int64_t seg[kCooParts + 1];
+  int parts;
+  int64_t nrows;
+};
+
+// Output row `row` of part p goes to row p * nrows + row of the partial
+// outputs (the output itself with one part); carry slots hold that key.
 template <int RL, int T>
-__global__ __launch_bounds__(256) void coo_mttkrp_kernel(const int4* __restrict__ ent, int64_t nnz, int L,
-                                                         int64_t nseg, const float* __restrict__ fa,
-                                                         const float* __restrict__ fb, int R,
-                                                         float* __restrict__ out, float* __restrict__ cval,
-                                                         int32_t* __restrict__ crow) {
+__global__ __launch_bounds__(256) void coo_mttkrp_kernel(const int4* __restrict__ ent, CooSegs sg, int L,
+                                                         const float* __restrict__ fa, const float* __restrict__ fb,
+                                                         int R, float* __restrict__ out, float* __restrict__ cval,
+                                                         int64_t* __restrict__ crow) {
   constexpr int G = kWave / RL;
   __shared__ int4 stage[4][kWave];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane / RL, c0 = lane % RL;
-  const int64_t seg = ((int64_t)blockIdx.x * 4 + w) * G + g;
-  if (seg >= nseg) return;
-  const int64_t e0 = seg * L, e1 = min(e0 + (int64_t)L, nnz);
+  // Workgroups are handed to the XCDs in turn, so workgroup b runs on XCD
+  // b mod 8: part p is walked by XCD p, whose L2 then holds that part's
+  // share of the gathered factor.
+  const int part = sg.parts > 1 ? (int)(blockIdx.x % (unsigned)sg.parts) : 0;
+  const int64_t lb = sg.parts > 1 ? blockIdx.x / (unsigned)sg.parts : blockIdx.x;
+  const int64_t ls = (lb * 4 + w) * G + g;
+  if (ls >= sg.seg[part + 1] - sg.seg[part]) return;
+  const int64_t seg = sg.seg[part] + ls;
+  const int64_t e0 = sg.ent[part] + ls * L, e1 = min(e0 + (int64_t)L, sg.ent[part + 1]);
+  const int64_t kbase = (int64_t)part * sg.nrows;
   int4* my = stage[w] + g * RL;
   float acc[T];
 #pragma unroll
@@ -268,9 +317,9 @@ __global__ __launch_bounds__(256) void coo_mttkrp_kernel(const int4* __restrict_
         if (q[u].x != cur) {
           if (first) {
             store_row<RL, T>(cval + (2 * seg) * R, acc, R, c0);
-            if (c0 == 0) crow[2 * seg] = (int32_t)cur;
+            if (c0 == 0) crow[2 * seg] = kbase + cur;
           } else {
-            store_row<RL, T>(out + cur * R, acc, R, c0);
+            store_row<RL, T>(out + (kbase + cur) * R, acc, R, c0);
           }
           first = false;
           cur = q[u].x;
@@ -288,28 +337,28 @@ __global__ __launch_bounds__(256) void coo_mttkrp_kernel(const int4* __restrict_
   if (first) {
     store_row<RL, T>(cval + (2 * seg) * R, acc, R, c0);
     if (c0 == 0) {
-      crow[2 * seg] = (int32_t)cur;
+      crow[2 * seg] = kbase + cur;
       crow[2 * seg + 1] = -1;
     }
   } else {
     store_row<RL, T>(cval + (2 * seg + 1) * R, acc, R, c0);
-    if (c0 == 0) crow[2 * seg + 1] = (int32_t)cur;
+    if (c0 == 0) crow[2 * seg + 1] = kbase + cur;
   }
 }
 
-// One level of the carry reduction.  The slots (row, R values; row -1 =
+// One level of the carry reduction.  The slots (key, R values; key -1 =
 // empty) are cut into groups of kCarryGroup consecutive slots, each walked
-// by RL lanes like a segment of entries: a row that starts and ends inside
-// the group is written to out, the group's first and last rows go to two
-// slots of the next level.  With a single group (final) every row is
+// by RL lanes like a segment of entries: a key that starts and ends inside
+// the group is written to out, the group's first and last keys go to two
+// slots of the next level.  With a single group (final) every key is
 // written.  Each level keeps the slot order, so a row's partial sums are
 // added in segment order along a tree fixed by nnz.
 constexpr int kCarryGroup = 32;
 
 template <int RL, int T>
-__global__ __launch_bounds__(256) void coo_carry_kernel(const float* __restrict__ cin, const int32_t* __restrict__ rin,
+__global__ __launch_bounds__(256) void coo_carry_kernel(const float* __restrict__ cin, const int64_t* __restrict__ rin,
                                                         int64_t nin, int final_, int R, float* __restrict__ out,
-                                                        float* __restrict__ cout, int32_t* __restrict__ rout) {
+                                                        float* __restrict__ cout, int64_t* __restrict__ rout) {
   constexpr int G = kWave / RL;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c0 = lane % RL;
@@ -323,7 +372,7 @@ __global__ __launch_bounds__(256) void coo_carry_kernel(const float* __restrict_
   int64_t cur = -1;
   bool first = true;
   for (int64_t k = s0; k < s1; ++k) {
-    const int32_t r = rin[k];
+    const int64_t r = rin[k];
     if (r < 0) continue;
     float v[T];
 #pragma unroll
@@ -334,7 +383,7 @@ __global__ __launch_bounds__(256) void coo_carry_kernel(const float* __restrict_
     if (cur >= 0 && r != cur) {
       if (first && !final_) {
         store_row<RL, T>(cout + (2 * gi) * R, acc, R, c0);
-        if (c0 == 0) rout[2 * gi] = (int32_t)cur;
+        if (c0 == 0) rout[2 * gi] = cur;
       } else {
         store_row<RL, T>(out + cur * R, acc, R, c0);
       }
@@ -351,12 +400,22 @@ __global__ __launch_bounds__(256) void coo_carry_kernel(const float* __restrict_
   } else if (first) {
     store_row<RL, T>(cout + (2 * gi) * R, acc, R, c0);
     if (c0 == 0) {
-      rout[2 * gi] = (int32_t)cur;
+      rout[2 * gi] = cur;
       rout[2 * gi + 1] = -1;
     }
   } else {
     store_row<RL, T>(cout + (2 * gi + 1) * R, acc, R, c0);
-    if (c0 == 0) rout[2 * gi + 1] = (int32_t)cur;
+    if (c0 == 0) rout[2 * gi + 1] = cur;
+  }
+}
+
+// out[e] = sum over parts p, in order, of part[p * n + e].
+__global__ __launch_bounds__(256) void coo_part_sum_kernel(const float* __restrict__ part, int parts, int64_t n,
+                                                           float* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    float s = part[e];
+    for (int p = 1; p < parts; ++p) s += part[p * n + e];
+    out[e] = s;
   }
 }
 
@@ -378,6 +437,18 @@ int coo_segment_len(int64_t nnz) {
   return (int)std::min<int64_t>(kCooMaxSeg, std::max<int64_t>(64, (want + 63) / 64 * 64));
 }
 
+// A mode may be partitioned when the partial outputs (one per part, each
+// zeroed, written and read: 3 x 8 x rows x R floats) stay small next to the
+// entries (16 bytes each): 8 x rows x 64 <= nnz.  A gathered factor
+// qualifies when it is large enough to overflow an XCD's 4 MB L2 (8192 rows
+// and more) but an eighth of it fits there at the usual ranks (at most
+// 131072 rows: 2 MB per part at R = 32).
+bool coo_may_partition(const int64_t dims[3], int64_t nnz, int mode) {
+  return (int64_t)kCooParts * dims[mode] * 64 <= nnz;
+}
+constexpr int64_t kCooPartMinRows = 8192;
+constexpr int64_t kCooPartMaxRows = 131072;
+
 }  // namespace mtk
 
 // ------------------------------------------------------------------ C ABI ---
@@ -387,13 +458,16 @@ struct mtk_coo {
   int64_t dims[3] = {0, 0, 0};
   int64_t nnz = 0;
   int seg_len = 64;
-  int64_t nseg = 0;
-  int4* ent[3] = {nullptr, nullptr, nullptr};  // per mode, sorted by that mode's index
-  float* cval = nullptr;                        // 2 * nseg carry slots of up to kMaxRank floats
-  int32_t* crow = nullptr;                      // their rows (-1: empty)
+  mtk::CooSegs segs[3] = {};                    // per mode: parts, entry and segment ranges
+  int64_t max_nseg = 0;                         // most segments of any mode
+  int4* ent[3] = {nullptr, nullptr, nullptr};  // per mode, sorted by (part, that mode's index)
+  float* cval = nullptr;                        // 2 * max_nseg carry slots of up to kMaxRank floats
+  int64_t* crow = nullptr;                      // their keys (-1: empty)
   float* cval2 = nullptr;                       // the next level's slots (levels alternate)
-  int32_t* crow2 = nullptr;
+  int64_t* crow2 = nullptr;
   void* block = nullptr;                        // the one allocation behind all of the above
+  float* part = nullptr;                        // partial outputs of a partitioned mode (grown on demand)
+  size_t part_bytes = 0;
 };
 
 namespace {
@@ -444,14 +518,15 @@ mtk_status mtk_coo_create(mtk_ctx* c, const int64_t dims[3], int64_t nnz, const 
   std::memcpy(t->dims, dims, sizeof(t->dims));
   t->nnz = nnz;
   t->seg_len = coo_segment_len(nnz);
-  t->nseg = (nnz + t->seg_len - 1) / t->seg_len;
+  // Segment count bound: each part rounds its segments up once.
+  t->max_nseg = (nnz + t->seg_len - 1) / t->seg_len + kCooParts;
   const size_t ent_b = up256((size_t)nnz * sizeof(int4));
-  const int64_t nslot = 2 * t->nseg;
+  const int64_t nslot = 2 * t->max_nseg;
   const int64_t nslot2 = 2 * ((nslot + kCarryGroup - 1) / kCarryGroup);
   const size_t cval_b = up256((size_t)nslot * kMaxRank * sizeof(float));
-  const size_t crow_b = up256((size_t)nslot * sizeof(int32_t));
+  const size_t crow_b = up256((size_t)nslot * sizeof(int64_t));
   const size_t cval2_b = up256((size_t)nslot2 * kMaxRank * sizeof(float));
-  const size_t crow2_b = up256((size_t)nslot2 * sizeof(int32_t));
+  const size_t crow2_b = up256((size_t)nslot2 * sizeof(int64_t));
   if ((e = hipMalloc(&t->block, 3 * ent_b + cval_b + crow_b + cval2_b + crow2_b + 256)) != hipSuccess) {
     delete t;
     return coo_hip_fail(c, e, "mtk_coo_create: allocation");
@@ -459,22 +534,27 @@ mtk_status mtk_coo_create(mtk_ctx* c, const int64_t dims[3], int64_t nnz, const 
   char* p = static_cast<char*>(t->block);
   for (int m = 0; m < 3; ++m, p += ent_b) t->ent[m] = reinterpret_cast<int4*>(p);
   t->cval = reinterpret_cast<float*>(p);
-  t->crow = reinterpret_cast<int32_t*>(p + cval_b);
+  t->crow = reinterpret_cast<int64_t*>(p + cval_b);
   t->cval2 = reinterpret_cast<float*>(p + cval_b + crow_b);
-  t->crow2 = reinterpret_cast<int32_t*>(p + cval_b + crow_b + cval2_b);
+  t->crow2 = reinterpret_cast<int64_t*>(p + cval_b + crow_b + cval2_b);
+  for (int m = 0; m < 3; ++m) {
+    CooSegs& sg = t->segs[m];
+    sg.parts = 1;
+    sg.nrows = dims[m];
+  }
   if (nnz == 0) {
     *out = t;
     return MTK_OK;
   }
 
   // Temporaries of the sort: ping-pong keys and payloads, digit histograms,
-  // scan block sums and the range-check counter.
+  // scan block sums, the range-check counter and the part counts.
   const int64_t ntiles = (nnz + kSortTile - 1) / kSortTile;
   const int64_t nhist = 256 * ntiles;
   const int64_t nsums = (nhist + kScanTile - 1) / kScanTile;
   const size_t kb = up256((size_t)nnz * 4);
   void* tmp = nullptr;
-  if ((e = hipMalloc(&tmp, 4 * kb + up256(nhist * 4) + up256(nsums * 4) + 256)) != hipSuccess) {
+  if ((e = hipMalloc(&tmp, 5 * kb + up256(nhist * 4) + up256(nsums * 4) + 512)) != hipSuccess) {
     hipFree(t->block);
     delete t;
     return coo_hip_fail(c, e, "mtk_coo_create: sort temporaries");
@@ -482,9 +562,11 @@ mtk_status mtk_coo_create(mtk_ctx* c, const int64_t dims[3], int64_t nnz, const 
   char* q = static_cast<char*>(tmp);
   int32_t* kbuf[2] = {reinterpret_cast<int32_t*>(q), reinterpret_cast<int32_t*>(q + kb)};
   int32_t* pbuf[2] = {reinterpret_cast<int32_t*>(q + 2 * kb), reinterpret_cast<int32_t*>(q + 3 * kb)};
-  int* hist = reinterpret_cast<int*>(q + 4 * kb);
-  int* sums = reinterpret_cast<int*>(q + 4 * kb + up256(nhist * 4));
-  int* bad = reinterpret_cast<int*>(q + 4 * kb + up256(nhist * 4) + up256(nsums * 4));
+  int32_t* pkey = reinterpret_cast<int32_t*>(q + 4 * kb);
+  int* hist = reinterpret_cast<int*>(q + 5 * kb);
+  int* sums = reinterpret_cast<int*>(q + 5 * kb + up256(nhist * 4));
+  int* bad = reinterpret_cast<int*>(q + 5 * kb + up256(nhist * 4) + up256(nsums * 4));
+  int* pcnt = bad + 64;
 
   auto done = [&](mtk_status s) {
     hipStreamSynchronize(st);
@@ -507,22 +589,64 @@ mtk_status mtk_coo_create(mtk_ctx* c, const int64_t dims[3], int64_t nnz, const 
   if (hbad != 0)
     return done(coo_fail(c, MTK_EINVAL, "mtk_coo_create: " + std::to_string(hbad) + " entries have an index outside dims"));
 
+  auto radix_pass = [&](const int32_t* keys, const int32_t* perm, int shift, int32_t* ko, int32_t* po) {
+    radix_hist_kernel<<<ntiles, kSortThreads, 0, st>>>(keys, nnz, shift, hist, ntiles);
+    scan_tiles_kernel<<<nsums, 256, 0, st>>>(hist, nhist, sums);
+    scan_sums_kernel<<<1, 256, 0, st>>>(sums, nsums);
+    scan_add_kernel<<<grid_of(nhist, 256), 256, 0, st>>>(hist, nhist, sums);
+    radix_scatter_kernel<<<ntiles, kSortThreads, 0, st>>>(keys, perm, nnz, shift, hist, ntiles, ko, po);
+  };
   for (int m = 0; m < 3; ++m) {
     const int oa = m == 0 ? 1 : 0, ob = m == 2 ? 1 : 2;
     const int passes = digit_passes(dims[m]);
     const int32_t* keys = idx[m];
     const int32_t* perm = nullptr;
-    for (int ps = 0; ps < passes; ++ps) {
-      const int shift = 8 * ps;
-      int32_t* ko = kbuf[ps & 1];
-      int32_t* po = pbuf[ps & 1];
-      radix_hist_kernel<<<ntiles, kSortThreads, 0, st>>>(keys, nnz, shift, hist, ntiles);
-      scan_tiles_kernel<<<nsums, 256, 0, st>>>(hist, nhist, sums);
-      scan_sums_kernel<<<1, 256, 0, st>>>(sums, nsums);
-      scan_add_kernel<<<grid_of(nhist, 256), 256, 0, st>>>(hist, nhist, sums);
-      radix_scatter_kernel<<<ntiles, kSortThreads, 0, st>>>(keys, perm, nnz, shift, hist, ntiles, ko, po);
-      keys = ko;
-      perm = po;
+    int buf = 0;
+    for (int ps = 0; ps < passes; ++ps, buf ^= 1) {
+      radix_pass(keys, perm, 8 * ps, kbuf[buf], pbuf[buf]);
+      keys = kbuf[buf];
+      perm = pbuf[buf];
+    }
+    CooSegs& sg = t->segs[m];
+    sg.parts = 1;
+    int64_t cnt[kCooParts] = {nnz};
+    if (coo_may_partition(dims, nnz, m)) {
+      // Of the two gathered factors, partition by the one whose index ranges
+      // spread the entries most evenly over the parts (a skewed index would
+      // leave one XCD most of the work); none if even that one is lopsided.
+      int best = -1;
+      int64_t best_max = 0;
+      int64_t best_cnt[kCooParts] = {};
+      for (int cand : {oa, ob}) {
+        if (dims[cand] < kCooPartMinRows || dims[cand] > kCooPartMaxRows) continue;
+        int hc[kCooParts] = {};
+        fill_zero_kernel<<<1, 64, 0, st>>>(reinterpret_cast<float*>(pcnt), kCooParts);
+        coo_part_count_kernel<<<grid_of(nnz, 256, 1024), 256, 0, st>>>(idx[cand], dims[cand], kCooParts, nnz, pcnt);
+        if ((e = hipMemcpyAsync(hc, pcnt, sizeof(hc), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+          return done(coo_hip_fail(c, e, "mtk_coo_create: part counts"));
+        const int64_t mx = *std::max_element(hc, hc + kCooParts);
+        if (best < 0 || mx < best_max) {
+          best = cand;
+          best_max = mx;
+          for (int pp = 0; pp < kCooParts; ++pp) best_cnt[pp] = hc[pp];
+        }
+      }
+      if (best >= 0 && best_max * 4 * kCooParts <= 5 * nnz) {
+        // One more stable pass orders the entries by part, rows ascending within each.
+        sg.parts = kCooParts;
+        coo_part_key_kernel<<<grid_of(nnz, 256), 256, 0, st>>>(perm, idx[best], dims[best], sg.parts, nnz, pkey);
+        radix_pass(pkey, perm, 0, kbuf[buf], pbuf[buf]);
+        perm = pbuf[buf];
+        for (int pp = 0; pp < kCooParts; ++pp) cnt[pp] = best_cnt[pp];
+      }
+    }
+    sg.ent[0] = 0;
+    sg.seg[0] = 0;
+    for (int pp = 0; pp < kCooParts; ++pp) {
+      const int64_t n = pp < sg.parts ? cnt[pp] : 0;
+      sg.ent[pp + 1] = sg.ent[pp] + n;
+      sg.seg[pp + 1] = sg.seg[pp] + (n + t->seg_len - 1) / t->seg_len;
     }
     coo_gather_kernel<<<grid_of(nnz, 256), 256, 0, st>>>(perm, idx[m], idx[oa], idx[ob], vals, nnz, t->ent[m]);
   }
@@ -537,6 +661,7 @@ mtk_status mtk_coo_destroy(mtk_coo* t) {
   hipGetDevice(&prev);
   hipSetDevice(t->device);
   hipFree(t->block);
+  if (t->part) hipFree(t->part);
   hipSetDevice(prev);
   delete t;
   return MTK_OK;
@@ -544,11 +669,12 @@ mtk_status mtk_coo_destroy(mtk_coo* t) {
 
 int64_t mtk_coo_nnz(const mtk_coo* t) { return t ? t->nnz : -1; }
 
-mtk_status mttkrp_coo(mtk_ctx* c, const mtk_coo* t, const float* const factors[3], int64_t R, int mode, float* out,
+mtk_status mttkrp_coo(mtk_ctx* c, const mtk_coo* tc, const float* const factors[3], int64_t R, int mode, float* out,
                       void* stream) {
   using namespace mtk;
   if (!c) return MTK_EINVAL;
-  if (!t || !factors || !out) return coo_fail(c, MTK_EINVAL, "NULL argument");
+  if (!tc || !factors || !out) return coo_fail(c, MTK_EINVAL, "NULL argument");
+  mtk_coo* t = const_cast<mtk_coo*>(tc);   // the partial-output buffer is grown on demand
   if (t->device != c->device) return coo_fail(c, MTK_EINVAL, "tensor and context are on different devices");
   if (mode < 0 || mode > 2) return coo_fail(c, MTK_EINVAL, "mode must be 0, 1 or 2");
   if (R < 1 || R > kMaxRank) return coo_fail(c, MTK_EINVAL, "R must be in [1, 128]");
@@ -558,26 +684,45 @@ mtk_status mttkrp_coo(mtk_ctx* c, const mtk_coo* t, const float* const factors[3
   if (e != hipSuccess) return coo_hip_fail(c, e, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t nrows = t->dims[mode];
-  fill_zero_kernel<<<grid_of(nrows * R, 256, 4096), 256, 0, st>>>(out, nrows * R);
+  const CooSegs& sg = t->segs[mode];
+  const bool parts = t->nnz > 0 && sg.parts > 1;
+  float* base = out;
+  if (parts) {
+    const size_t need = (size_t)sg.parts * nrows * R * sizeof(float);
+    if (need > t->part_bytes) {
+      if (t->part) {
+        hipFree(t->part);          // waits for the work that used it
+        t->part = nullptr;
+        t->part_bytes = 0;
+      }
+      if ((e = hipMalloc(&t->part, need)) != hipSuccess) return coo_hip_fail(c, e, "mttkrp_coo: partial outputs");
+      t->part_bytes = need;
+    }
+    base = t->part;
+  }
+  const int64_t nbase = (parts ? sg.parts : 1) * nrows * R;
+  fill_zero_kernel<<<grid_of(nbase, 256, 4096), 256, 0, st>>>(base, nbase);
   if (t->nnz > 0) {
     const int r = (int)R;
     const int4* ent = t->ent[mode];
     const float* fa = factors[oa];
     const float* fb = factors[ob];
-    const int64_t nslot = 2 * t->nseg;
+    const int64_t nslot = 2 * sg.seg[kCooParts];
+    int64_t most = 0;
+    for (int pp = 0; pp < sg.parts; ++pp) most = std::max<int64_t>(most, sg.seg[pp + 1] - sg.seg[pp]);
 #define MTK_COO_LAUNCH(RL, T)                                                                           \
   do {                                                                                                  \
     const int64_t gpb = 4 * (kWave / RL);                                                               \
-    coo_mttkrp_kernel<RL, T><<<(t->nseg + gpb - 1) / gpb, 256, 0, st>>>(ent, t->nnz, t->seg_len, t->nseg, \
-                                                                        fa, fb, r, out, t->cval, t->crow); \
+    coo_mttkrp_kernel<RL, T><<<sg.parts * ((most + gpb - 1) / gpb), 256, 0, st>>>(ent, sg, t->seg_len, fa, \
+                                                                                  fb, r, base, t->cval, t->crow); \
     float* cv[2] = {t->cval, t->cval2};                                                                 \
-    int32_t* cr[2] = {t->crow, t->crow2};                                                               \
+    int64_t* cr[2] = {t->crow, t->crow2};                                                               \
     int64_t nin = nslot;                                                                                \
     for (int lv = 0;; ++lv) {                                                                           \
       const int64_t groups = (nin + kCarryGroup - 1) / kCarryGroup;                                     \
       const int fin = groups == 1;                                                                      \
       coo_carry_kernel<RL, T><<<(groups + gpb - 1) / gpb, 256, 0, st>>>(                                \
-          cv[lv & 1], cr[lv & 1], nin, fin, r, out, cv[(lv + 1) & 1], cr[(lv + 1) & 1]);                \
+          cv[lv & 1], cr[lv & 1], nin, fin, r, base, cv[(lv + 1) & 1], cr[(lv + 1) & 1]);               \
       if (fin) break;                                                                                   \
       nin = 2 * groups;                                                                                 \
     }                                                                                                   \
@@ -593,6 +738,7 @@ mtk_status mttkrp_coo(mtk_ctx* c, const mtk_coo* t, const float* const factors[3
     else
       MTK_COO_LAUNCH(64, 2);
 #undef MTK_COO_LAUNCH
+    if (parts) coo_part_sum_kernel<<<grid_of(nrows * R, 256, 4096), 256, 0, st>>>(base, sg.parts, nrows * R, out);
   }
   if ((e = hipGetLastError()) != hipSuccess) return coo_hip_fail(c, e, "mttkrp_coo launch");
   return MTK_OK;

@@ -209,3 +209,18 @@ def test_sparse_cp_als_matches_oracle(ctx):
     _say(f"fit {gfit:.9f} oracle {ofits[-1]:.9f} model {me:.2e}")
     assert abs(gfit - ofits[-1]) <= 1e-4
     assert me <= 1e-3
+
+
+@pytest.mark.parametrize("R", [8, 64, 100])
+def test_partitioned_modes_exact(ctx, R):
+    # A large second mode makes mode 0 partitioned (entries ordered by which
+    # eighth of B's rows they gather, one partial output per part, added in
+    # part order); integer inputs, so bit for bit, with power-law rows too.
+    # (20000, 200, 9000) with a power-law mode-0 index: mode 1 partitions by
+    # the mode-2 index, which spreads its entries evenly, not by the skewed one.
+    for dims, skew in (((200, 10000, 9000), None), ((200, 10000, 9000), 1.3), ((20000, 200, 9000), 1.3)):
+        idx, vals = synth.coo(dims, 120001, seed=300 + R, skew=skew, integer=True)
+        facs = synth.integer_factors(301 + R, dims, R)
+        outs = _run(ctx, dims, idx, vals, facs)
+        for mode, got in enumerate(outs):
+            assert np.array_equal(got, oracle.mttkrp_coo(idx, vals, dims, facs, mode)), (dims, R, skew, mode)
