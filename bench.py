@@ -25,14 +25,15 @@ full MTTKRPs also give each path's per-mode error over every output row.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
                     [--workload cp1024_r64|cp512_r32|cp768_r128_sliced|cp64_r8|serve|copy|
-                                coo64k_nnz64m_r64|coo64k_nnz64m_r64_zipf]
+                                coo64k_nnz64m_r64|coo64k_nnz64m_r64_zipf|nway4_128_r32]
                     [--prec fp32|bf16x3|bf16x6|fp8] [--compare fp32[,bf16x6]|none] [--no-cpu-baseline]
 
 ``--workload cp768_r128_sliced`` (FP8 e4m3, per-slice scales) also runs the
 workload's 20 CP-ALS sweeps and reports their fit and model against the
 oracle's 20 sweeps (``tests/golden/cp768_r128_als.json``, written by the
 oracle).  ``--workload serve`` runs the serving workload instead (see
-serve_bench); the ``coo*`` workloads run sparse CP-ALS (see sparse_bench).
+serve_bench); the ``coo*`` workloads run sparse CP-ALS (see sparse_bench) and
+``nway4_128_r32`` four-way CP-ALS (see nway_bench).
 """
 
 from __future__ import annotations
@@ -443,6 +444,93 @@ def sparse_bench(args):
     t.close()
 
 
+NWAY_WORKLOADS = {
+    # dims, rank of the CP tensor, R, noise variance
+    "nway4_128_r32": ((128, 128, 128, 128), 32, 32, 1e-4),
+}
+
+
+def nway_bench(args):
+    """Order-N CP-ALS on one MI355X: a step is one sweep of als_sweep_nway
+    (every mode: the merged groups' Khatri-Rao rows, the three-way
+    contraction of the view, the update) over a seeded 4-way CP tensor."""
+    import torch
+    import oracle
+    from paper_2411_04785_amd import synth
+    from paper_2411_04785_amd.mttkrp import Context
+    dims, rank, R, nv = NWAY_WORKLOADS[args.workload]
+    prec = args.prec or "bf16x3"
+    t0 = time.perf_counter()
+    X, init = synth.cp_nway(dims, rank, R, seed=2413, noise_var=nv)
+    log(f"[bench] {args.workload}: inputs drawn in {time.perf_counter() - t0:.1f} s")
+    ctx = Context(0)
+    stream = torch.cuda.current_stream()
+    Xd = torch.from_numpy(X).cuda()
+    f0 = [torch.from_numpy(f).cuda() for f in init]
+    n = len(dims)
+    numel = float(np.prod(dims))
+    flop_mttkrp = 2.0 * numel * R
+    paths = [prec] + [p for p in ("fp32",) if p != prec]
+    res = {}
+    for p in paths:
+        mode_ms, outs = [], []
+        for mode in range(n):
+            out = ctx.mttkrp_nway(Xd, f0, mode, p)
+            mode_ms.append(time_calls(torch, stream, lambda: ctx.mttkrp_nway(Xd, f0, mode, p, out=out),
+                                      args.mode_reps))
+            outs.append(out.cpu().numpy().astype(np.float64))
+        fd = [f.clone() for f in f0]
+        lam = torch.ones(R, dtype=torch.float64, device="cuda")
+        ctx.als_sweep_nway(Xd, fd, lam, max(1, args.warmup), p)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch, stream)
+        e0.record(stream)
+        ctx.als_sweep_nway(Xd, fd, lam, args.steps, p)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[p] = {"mode_ms": mode_ms, "outs": outs, "ms_step": e0.elapsed_time(e1) / args.steps}
+        log(f"[bench] {p}: per mode {[round(x * 1e3, 1) for x in mode_ms]} us, sweep {res[p]['ms_step']:.3f} ms")
+    refs = [oracle.mttkrp_nway(X, init, mode) for mode in range(n)]
+    head = res[prec]
+    m = int(np.argmax(head["mode_ms"]))
+    others = sum(d for k, d in enumerate(dims) if k != m)
+    nbytes = 4 * numel + 4 * R * others + 4 * dims[m] * R
+    ach = nbytes / (head["mode_ms"][m] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"mode-{m + 1} N-way MTTKRP (Khatri-Rao rows + contraction of the three-way view)",
+            "avg_launch_us": round(head["mode_ms"][m] * 1e3, 2), "algorithmic_bytes": int(nbytes)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        ts = []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            oracle.mttkrp_nway(X, init, 0)
+            ts.append(time.perf_counter() - c0)
+        med = float(np.median(ts))
+        cpu = {"value": round(flop_mttkrp / med / 1e9, 2), "unit": "GFLOP/s", "cores": int(blas_threads()),
+               "kind": "oracle", "sample": f"FP64 oracle mode-1 N-way MTTKRP (unfolding x explicit Khatri-Rao "
+                                           f"product, BLAS) of the same tensor, median of 3 runs: "
+                                           f"{', '.join(f'{x:.2f}' for x in ts)} s"}
+    detail = {}
+    for p, r in res.items():
+        errs = [float(np.linalg.norm(o - ref) / np.linalg.norm(ref)) for o, ref in zip(r["outs"], refs)]
+        detail[p] = {"ms_per_sweep": round(r["ms_step"], 4), "mttkrp_us": [round(x * 1e3, 1) for x in r["mode_ms"]],
+                     "mttkrp_gbs": [round((4 * numel + 4 * R * (sum(dims) - dims[k]) + 4 * dims[k] * R)
+                                          / (t * 1e-3) / 1e9, 1) for k, t in enumerate(r["mode_ms"])],
+                     "err_rel_per_mode": [float(f"{e:.3e}") for e in errs]}
+    if "fp32" in res and prec != "fp32":
+        detail["sweep_speedup_vs_fp32"] = round(res["fp32"]["ms_step"] / head["ms_step"], 3)
+    print(json.dumps({
+        "metric": "N-way MTTKRP GFLOP/s (algorithmic, N x 2*prod(dims)*R per CP-ALS sweep)",
+        "value": round(n * flop_mttkrp / (head["ms_step"] * 1e-3) / 1e9, 1), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": args.workload, "dims": list(dims), "rank_true": rank, "R": R, "prec": prec},
+        "roofline": roof, "cpu_baseline": cpu, "detail": detail}), flush=True)
+    ctx.close()
+
+
 def _events(torch, stream):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -601,6 +689,9 @@ def main():
         return
     if args.workload in SPARSE_WORKLOADS:
         sparse_bench(args)
+        return
+    if args.workload in NWAY_WORKLOADS:
+        nway_bench(args)
         return
 
     import torch

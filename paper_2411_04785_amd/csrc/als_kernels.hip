@@ -47,46 +47,81 @@ constexpr int kApplyRows = 16;
 __host__ __device__ inline size_t gram_part_elems(int R) { return (size_t)gram_pairs(R) * kGramBlocksMax * 256; }
 
 
+typedef __attribute__((ext_vector_type(4))) double gram_d4;
+
+// Gram tile over rows [i0, i1) on FP64 MFMA (16x16x4): rows are taken in
+// chunks of 64, wave w of the workgroup owning rows c0 + 16w + 4s + g of a
+// chunk (step s = 0..3, g = lane / 16), lane (n, g) holding column tr*16 + n
+// as the A operand and ts*16 + n as the B operand, so the 16 x 16 x 4 product
+// adds four rows' outer products; step s accumulates into acc[s].  S chunks
+// are loaded at once and the next S are in flight while these are summed.
+// The accumulation order does not depend on S (acc[s] takes the chunks in
+// increasing order).  Result layout (FP64 16x16x4, measured on the device):
+// lane (n, g) receives tile rows g + 4v, column n.
+template <int S, class Load, class Conv, class Emit>
+__device__ void gram_tile_mfma(int64_t i0, int64_t i1, int R, int tr, int ts, Load load, Conv conv, Emit emit,
+                               gram_d4 acc[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nn = lane & 15, g = lane >> 4;
+  const int cr = tr * 16 + nn, cs = ts * 16 + nn;
+  const int crl = min(cr, R - 1), csl = min(cs, R - 1);
+  using Raw = decltype(load(int64_t(0), 0));
+  Raw ra[S][4], rb[S][4];
+  auto fetch = [&](int64_t c0) {
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t i = min(c0 + 64 * q + 16 * w + 4 * s + g, i1 - 1);
+        ra[q][s] = load(i, crl);
+        rb[q][s] = load(i, csl);  // unused on a diagonal tile (a branch here would wait on the loads)
+      }
+  };
+  if (i0 < i1) fetch(i0);
+  for (int64_t c0 = i0; c0 < i1; c0 += 64 * S) {
+    double a[S][4], b[S][4];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t i = c0 + 64 * q + 16 * w + 4 * s + g;
+        float va = 0.f, vb = 0.f;
+        if (i < i1 && cr < R) { va = conv(ra[q][s], cr); emit(i, cr, va); }
+        if (i < i1 && cs < R) vb = tr == ts ? va : conv(rb[q][s], cs);
+        a[q][s] = va;
+        b[q][s] = vb;
+      }
+    if (c0 + 64 * S < i1) fetch(c0 + 64 * S);
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][s], b[q][s], acc[s], 0, 0, 0);
+  }
+}
+
 // Accumulate the Gram tile (rows tr*16.., cols ts*16..) over rows [i0, i1) of
-// a factor staged 64 rows at a time: load(i, col) reads the stored value
-// (as double) and conv(raw, col) turns it into the FP32 factor value.
-// Thread (r, s) = (tid >> 4, tid & 15) sums in increasing row order; both
-// Gram kernels use this one routine, so they agree bit for bit.  A chunk's
-// loads use clamped in-range indices and all go out before any is used.
+// a factor: load(i, col) reads the stored value and conv(raw, col) turns it
+// into the FP32 factor value (emit(i, col, v) sees each value of a diagonal
+// tile once).  Returns tile element (tid / 16, tid % 16) to thread tid: the
+// four steps' sums added in order, then the four waves' in order.  Both Gram
+// kernels use this one routine, so they agree bit for bit.  Row blocks of
+// 1024 rows or more load four chunks at a time, shorter ones two.
 template <class Load, class Conv, class Emit>
 __device__ double gram_tile_rows(int64_t i0, int64_t i1, int R, int tr, int ts, Load load, Conv conv, Emit emit) {
-  __shared__ float rows_r[64][17];
-  __shared__ float rows_s[64][17];
-  double acc = 0.0;
-  const int tid = threadIdx.x;
-  const int cc = tid & 15;
-  const int cr = tr * 16 + cc, cs = ts * 16 + cc;
-  const int crl = min(cr, R - 1), csl = min(cs, R - 1);
-  for (int64_t c0 = i0; c0 < i1; c0 += 64) {
-    double rr[4], rs[4];
+  __shared__ double red[4][256];
+  gram_d4 acc[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t i = min(c0 + (tid >> 4) + 16 * u, i1 - 1);
-      rr[u] = load(i, crl);
-      rs[u] = tr == ts ? 0.0 : load(i, csl);
-    }
+  for (int s = 0; s < 4; ++s) acc[s] = gram_d4{0.0, 0.0, 0.0, 0.0};
+  if (i1 - i0 >= 1024) gram_tile_mfma<4>(i0, i1, R, tr, ts, load, conv, emit, acc);
+  else gram_tile_mfma<2>(i0, i1, R, tr, ts, load, conv, emit, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int ii = (tid >> 4) + 16 * u;
-      const int64_t i = c0 + ii;
-      float vr = 0.f, vs = 0.f;
-      if (i < i1 && cr < R) { vr = conv(rr[u], cr); emit(i, cr, vr); }
-      if (i < i1 && cs < R) vs = tr == ts ? vr : conv(rs[u], cs);
-      rows_r[ii][cc] = vr;
-      rows_s[ii][cc] = vs;
-    }
-    __syncthreads();
-    const int cnt = (int)min<int64_t>(64, i1 - c0);
-    for (int ii = 0; ii < cnt; ++ii)
-      acc = fma((double)rows_r[ii][tid >> 4], (double)rows_s[ii][tid & 15], acc);
-    __syncthreads();
-  }
-  return acc;
+  for (int v = 0; v < 4; ++v)
+    red[w][((lane >> 4) + 4 * v) * 16 + (lane & 15)] = ((acc[0][v] + acc[1][v]) + acc[2][v]) + acc[3][v];
+  __syncthreads();
+  const int t = threadIdx.x;
+  const double r = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+  __syncthreads();
+  return r;
 }
 
 // Partial of tile `tile` over row block `rb`, stored as [tile][rb][16 x 16].
@@ -109,8 +144,8 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ F0,
   const int64_t rows = gram_rows(n, R);
   const int64_t i0 = (int64_t)rb * rows, i1 = min(n, i0 + rows);
   const double acc = gram_tile_rows(
-      i0, i1, R, tr, ts, [&](int64_t i, int c) { return (double)F[i * R + c]; },
-      [](double v, int) { return (float)v; }, [](int64_t, int, float) {});
+      i0, i1, R, tr, ts, [&](int64_t i, int c) { return F[i * R + c]; }, [](float v, int) { return v; },
+      [](int64_t, int, float) {});
   gram_store(acc, f ? P1 : P0, blockIdx.x, rb);
 }
 
@@ -253,16 +288,16 @@ __device__ __forceinline__ void normalize_gram_body(const double* __restrict__ F
   tile_pair(bx, tr, ts);
   const int tid = threadIdx.x;
   if (ipsum && bx == 0 && by == 0) {
-    // <F, M> over the whole factor: strided per-thread sums, then a tree, in
-    // fixed order.
+    // <F, M> over the whole factor: strided per-thread sums (32 loads in
+    // flight), then a tree, in fixed order.
     const int64_t ne = (int64_t)nblk * R;
     double t = 0.0;
-    for (int64_t e0 = tid; e0 < ne; e0 += 256 * 8) {
-      double v[8];
+    for (int64_t e0 = tid; e0 < ne; e0 += 256 * 32) {
+      double v[32];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = ipsum[min(e0 + 256 * u, ne - 1)];
+      for (int u = 0; u < 32; ++u) v[u] = ipsum[min(e0 + 256 * u, ne - 1)];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 32; ++u)
         if (e0 + 256 * u < ne) t += v[u];
     }
     ired[tid] = t;
@@ -276,17 +311,18 @@ __device__ __forceinline__ void normalize_gram_body(const double* __restrict__ F
   const bool diag = tr == ts;
   {
     // Column u of the tile pair (u < 16: tr, else ts): thread (q, u) sums
-    // row blocks b = q, q + 8, ... in order.
+    // row blocks b = q, q + 8, ... in order, 32 loads in flight (a factor
+    // of 65536 rows has 4096 row blocks).
     const int u = tid & 31, q = tid >> 5;
     const int col = (u < 16 ? tr : ts) * 16 + (u & 15);
     const int cl = min(col, R - 1);
     double t = 0.0;
-    for (int b0 = q; b0 < nblk; b0 += 64) {
-      double v[8];
+    for (int b0 = q; b0 < nblk; b0 += 256) {
+      double v[32];
 #pragma unroll
-      for (int w = 0; w < 8; ++w) v[w] = colsq[(int64_t)min(b0 + 8 * w, nblk - 1) * R + cl];
+      for (int w = 0; w < 32; ++w) v[w] = colsq[(int64_t)min(b0 + 8 * w, nblk - 1) * R + cl];
 #pragma unroll
-      for (int w = 0; w < 8; ++w)
+      for (int w = 0; w < 32; ++w)
         if (col < R && b0 + 8 * w < nblk) t += v[w];
     }
     lsum[q][u] = t;

@@ -259,3 +259,21 @@ def integer_factors(seed: int, dims: Sequence[int], R: int, lo: int = -4, hi: in
     """Factor matrices with integer entries in [lo, hi] (float32)."""
     return [rng(seed, STREAM_INIT, m).integers(lo, hi + 1, (int(d), R)).astype(np.float32)
             for m, d in enumerate(dims)]
+
+
+def cp_nway(dims: Sequence[int], rank: int, R: int, seed: int, noise_var: float = 0.0):
+    """An N-way CP tensor of the given rank plus N(0, noise_var) noise, FP32,
+    and N(0,1) starting factors (FP32) of rank R.  Built through its mode-1
+    unfolding: X_(1) = A (Khatri-Rao product of the other true factors)^T, the
+    first remaining mode's index slowest (row-major order of X)."""
+    g = rng(seed, STREAM_FACTORS)
+    facs = [g.standard_normal((int(d), rank)) for d in dims]
+    kr = facs[1]
+    for F in facs[2:]:
+        kr = (kr[:, None, :] * F[None, :, :]).reshape(-1, rank)
+    X = (facs[0] @ kr.T).reshape([int(d) for d in dims])
+    if noise_var > 0:
+        X += math.sqrt(noise_var) * rng(seed, STREAM_NOISE).standard_normal(X.shape)
+    gi = rng(seed, STREAM_INIT)
+    init = [gi.standard_normal((int(d), R)).astype(np.float32) for d in dims]
+    return X.astype(np.float32), init
