@@ -104,15 +104,21 @@ __device__ void gram_tile_mfma(int64_t i0, int64_t i1, int R, int tr, int ts, Lo
 // tile once).  Returns tile element (tid / 16, tid % 16) to thread tid: the
 // four steps' sums added in order, then the four waves' in order.  Both Gram
 // kernels use this one routine, so they agree bit for bit.  Row blocks of
-// 1024 rows or more load four chunks at a time, shorter ones two.
-template <class Load, class Conv, class Emit>
+// 1024 rows or more load four chunks at a time, shorter ones two (at most
+// MAXS: the grouped serving kernel, whose factors are short, takes one and
+// so keeps its registers low).
+template <int MAXS = 4, class Load, class Conv, class Emit>
 __device__ double gram_tile_rows(int64_t i0, int64_t i1, int R, int tr, int ts, Load load, Conv conv, Emit emit) {
   __shared__ double red[4][256];
   gram_d4 acc[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) acc[s] = gram_d4{0.0, 0.0, 0.0, 0.0};
-  if (i1 - i0 >= 1024) gram_tile_mfma<4>(i0, i1, R, tr, ts, load, conv, emit, acc);
-  else gram_tile_mfma<2>(i0, i1, R, tr, ts, load, conv, emit, acc);
+  if constexpr (MAXS >= 4) {
+    if (i1 - i0 >= 1024) gram_tile_mfma<4>(i0, i1, R, tr, ts, load, conv, emit, acc);
+    else gram_tile_mfma<2>(i0, i1, R, tr, ts, load, conv, emit, acc);
+  } else {
+    gram_tile_mfma<MAXS>(i0, i1, R, tr, ts, load, conv, emit, acc);
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int v = 0; v < 4; ++v)
@@ -274,6 +280,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const float* __restrict__ M,
 // the workgroups of diagonal tiles write the factor's columns of their tile,
 // and those of row block 0 write lambda.
 // Workgroup (bx = tile pair, by = row block) of the normalise launch.
+template <int MAXS = 4>
 __device__ __forceinline__ void normalize_gram_body(const double* __restrict__ F, int64_t n, int R,
                                                     const double* __restrict__ colsq, int nblk,
                                                     const int* __restrict__ status, double* __restrict__ lam,
@@ -348,7 +355,7 @@ __device__ __forceinline__ void normalize_gram_body(const double* __restrict__ F
   auto emit = [&](int64_t i, int col, float v) {
     if (diag) out[i * R + col] = v;
   };
-  const double acc = gram_tile_rows(i0, i1, R, tr, ts, load, conv, emit);
+  const double acc = gram_tile_rows<MAXS>(i0, i1, R, tr, ts, load, conv, emit);
   gram_store(acc, part, bx, rb);
 }
 
@@ -437,7 +444,7 @@ __global__ __launch_bounds__(256) void srv_normalize_kernel(const SrvTable* __re
     const SrvUpdate& u = t->e[q][upd].u;
     const int64_t local = w - t->e[q][upd].nb0;
     const int np = gram_pairs(u.R);
-    normalize_gram_body(u.F, u.n, u.R, u.colsq, u.nblk, u.status, u.lam, u.fout, u.gram_out, nullptr, nullptr,
+    normalize_gram_body<1>(u.F, u.n, u.R, u.colsq, u.nblk, u.status, u.lam, u.fout, u.gram_out, nullptr, nullptr,
                         (int)(local % np), (int)(local / np));
     __syncthreads();
   }

@@ -104,10 +104,37 @@ __device__ __forceinline__ void stage_weights(float* wl, const float* w, int n, 
   }
 }
 
+// Most 16-column MFMA tiles one FP8 wave holds (its two-term fragment takes
+// 16 VGPRs per tile at nv = 32); waves of a workgroup split wider ranks.
+// Eight: up to R = 128 one wave holds every column tile (128 fragment
+// VGPRs), because two waves sharing an X tile each load it, and those
+// duplicate loads cost more than the lost occupancy (768^3: 16-row x
+// 128-byte tiles stream at 3.7 TB/s loaded twice, 5.3-5.7 TB/s once, the
+// latter also at one workgroup per CU).
+#ifndef MTK_FP8_NTW
+#define MTK_FP8_NTW 8
+#endif
+// FP8 waves of more than four column tiles, held to two waves per SIMD so
+// that one wave's epilogue issues while the other's MFMAs run (1: one wave
+// per SIMD, with the epilogue interleaved into the MFMAs instead).
+#ifndef MTK_FP8_WIDE_WAVES
+#define MTK_FP8_WIDE_WAVES 2
+#endif
+// Most fragment VGPRs per lane an FP8 plan gives a wave (sets its nv; nv
+// does not go below 32).
+#ifndef MTK_FP8_FRAG_REGS
+#define MTK_FP8_FRAG_REGS 64
+#endif
+
 // Tiles kept in flight per wave: deeper for small tiles so that every CU has
 // enough bytes outstanding to cover the HBM latency.
 #ifndef MTK_PIPE_FP8
 #define MTK_PIPE_FP8 4
+#endif
+// Tiles in flight of an FP8 wave holding more than four column tiles: at
+// two waves per SIMD its fragment leaves room for two (a third spills).
+#ifndef MTK_PIPE_FP8_WIDE
+#define MTK_PIPE_FP8_WIDE 2
 #endif
 #ifndef MTK_PIPE_SMALL
 #define MTK_PIPE_SMALL 3
@@ -241,7 +268,7 @@ __device__ __forceinline__ void contract_body(const KArgs& a, int bid, float* dy
   // the block re-read its last tile instead of branching.
   auto run = [&](auto full_tag) {
     constexpr bool FULL = decltype(full_tag)::value;
-    constexpr int D = PipeDepth<PREC, NV>::value;
+    constexpr int D = (PREC == MTK_FP8_E4M3 && NT > 4) ? MTK_PIPE_FP8_WIDE : PipeDepth<PREC, NV>::value;
     if (l0 >= l1) return;
     XRegs<PREC, NV> x[D];
     // The prologue loads stay in tile order: the loop head's wait is shared
@@ -263,8 +290,78 @@ __device__ __forceinline__ void contract_body(const KArgs& a, int bid, float* dy
       }
     }
   };
-  if (tile_full) run(std::true_type{});
-  else run(std::false_type{});
+  // Built for one wave per SIMD (MTK_FP8_WIDE_WAVES = 1), FP8 with more than
+  // four column tiles per wave has nothing else to cover its epilogue: the
+  // MFMAs of step s are issued between the FMAs of step s - 1 (its products
+  // in Tp, its weights in wp, read from LDS at the end of step s - 1 and
+  // first used in step s, so that no LDS wait falls among the MFMAs).  Same
+  // products, same order of the FMAs into acc as `run`.
+  auto run_pipe = [&](auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    constexpr int D = MTK_PIPE_FP8_WIDE;
+    if (l0 >= l1) return;
+    XRegs<PREC, NV> x[D];
+#pragma unroll
+    for (int d = 0; d < D - 1; ++d) {
+      load_x<PREC, NV, CONTIG, VEC, FULL>(x[d], a.X, off0 + (int64_t)min(l0 + d, l1 - 1) * a.sLoop, a.sRed,
+                                          row_ok, red0, a.nRed);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    int colc[NT];
+    bool colv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = cb + t * 16 + m_l;
+      colc[t] = min(col, a.R - 1);
+      colv[t] = col < a.R;
+    }
+    f4 Tp[NT];
+    float wp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) { Tp[t] = zero4(); wp[t] = 0.f; }
+    for (int it = l0; it < l1; it += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int nx = min(it + d + D - 1, l1 - 1);
+        load_x<PREC, NV, CONTIG, VEC, FULL>(x[(d + D - 1) % D], a.X, off0 + (int64_t)nx * a.sLoop, a.sRed,
+                                            row_ok, red0, a.nRed);
+        __builtin_amdgcn_sched_barrier(0);
+        if (it + d < l1) {
+          f4 Tc[NT];
+          tile_mfma<PREC, NT, NV>(Tc, x[d], fr);
+          // Step l0 has no predecessor: Tp and wp are zero, and acc + 0 * 0 is acc.
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][v] = fmaf(colv[t] ? wp[t] : 0.f, Tp[t][v], acc[t][v]);
+#pragma unroll
+          for (int i = 0; i < 2 * NT * (NV / 32); ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // two VALU
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          const float* wr = wl + (it + d - l0) * a.R;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            Tp[t] = Tc[t];
+            wp[t] = wr[colc[t]];   // its select waits for the next step
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[t][v] = fmaf(colv[t] ? wp[t] : 0.f, Tp[t][v], acc[t][v]);
+  };
+  if constexpr (PREC == MTK_FP8_E4M3 && NT > 4 && MTK_FP8_WIDE_WAVES == 1) {
+    if (tile_full) run_pipe(std::true_type{});
+    else run_pipe(std::false_type{});
+  } else {
+    if (tile_full) run(std::true_type{});
+    else run(std::false_type{});
+  }
 
   // FP8 mode 0: each output row is a slice i; apply its power-of-two scale.
   if constexpr (PREC == MTK_FP8_E4M3) {
@@ -321,6 +418,22 @@ __global__ __launch_bounds__(256) void contract_kernel(KArgs a) {
     if (run_job(a, dyn_lds)) return;
   }
   contract_body<PREC, NT, NV, CONTIG, VEC>(a, (int)blockIdx.x - a.job_on, dyn_lds);
+}
+
+// (The byte-wise load forms, for unaligned or strided X, do not fit two
+// waves without spilling and keep one.)
+template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VEC ? MTK_FP8_WIDE_WAVES : 1)))
+void contract_wide_kernel(KArgs a) {
+  extern __shared__ float dyn_lds[];
+  contract_body<PREC, NT, NV, CONTIG, VEC>(a, (int)blockIdx.x - a.job_on, dyn_lds);
+}
+template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
+constexpr const void* contract_entry() {
+  if constexpr (PREC == MTK_FP8_E4M3 && NT > 4)
+    return reinterpret_cast<const void*>(&contract_wide_kernel<PREC, NT, NV, CONTIG, VEC>);
+  else
+    return reinterpret_cast<const void*>(&contract_kernel<PREC, NT, NV, CONTIG, VEC>);
 }
 
 // ---------------------------------------------------------------------------
@@ -690,7 +803,10 @@ template <int PREC, int NT, int NV, bool CONTIG, bool VEC>
 hipError_t launch_one(const KArgs& a, int64_t grid, hipStream_t st) {
   size_t lds = ((size_t)a.loop_block * a.R + (a.wr > 1 ? 4 * NT * 4 * 64 : 0)) * sizeof(float);
   with_job(a, grid, lds);
-  hipLaunchKernelGGL((contract_kernel<PREC, NT, NV, CONTIG, VEC>), dim3((unsigned)grid), dim3(256), lds, st, a);
+  if constexpr (PREC == MTK_FP8_E4M3 && NT > 4)
+    hipLaunchKernelGGL((contract_wide_kernel<PREC, NT, NV, CONTIG, VEC>), dim3((unsigned)grid), dim3(256), lds, st, a);
+  else
+    hipLaunchKernelGGL((contract_kernel<PREC, NT, NV, CONTIG, VEC>), dim3((unsigned)grid), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
@@ -751,6 +867,12 @@ hipError_t dispatch_nt(const KArgs& a, const ContractPlan& p, hipStream_t st) {
       case 2: return dispatch_nv<PREC, 2>(a, p, st);
       case 3: return dispatch_nv<PREC, 3>(a, p, st);
       case 4: return dispatch_nv<PREC, 4>(a, p, st);
+#if MTK_FP8_NTW > 4
+      case 5: return dispatch_nv<PREC, 5>(a, p, st);
+      case 6: return dispatch_nv<PREC, 6>(a, p, st);
+      case 7: return dispatch_nv<PREC, 7>(a, p, st);
+      case 8: return dispatch_nv<PREC, 8>(a, p, st);
+#endif
     }
     return hipErrorInvalidValue;
   } else {
@@ -791,15 +913,6 @@ constexpr int64_t kMaxGridX = 0x7fffffff;
 #ifndef MTK_CM_NTW
 #define MTK_CM_NTW 4
 #endif
-// Most 16-column MFMA tiles one FP8 wave holds (its two-term fragment takes
-// 16 VGPRs per tile); waves of a workgroup split wider ranks.
-#ifndef MTK_FP8_NTW
-#define MTK_FP8_NTW 4
-#endif
-// Most fragment VGPRs per lane an FP8 plan gives a wave (sets its nv).
-#ifndef MTK_FP8_FRAG_REGS
-#define MTK_FP8_FRAG_REGS 64
-#endif
 
 // Column length of the padded FP8 fragment codes: every window of the plan.
 inline int frag_red_pad(const ContractPlan& p) { return p.n_rg * p.wr * p.kw; }
@@ -818,8 +931,8 @@ const void* kernel_of_nt(const ContractPlan& p) {
   const bool c = p.sRed == 1;
   auto pick = [&](auto nv_tag) -> const void* {
     constexpr int NV = decltype(nv_tag)::value;
-    if (c) return reinterpret_cast<const void*>(&contract_kernel<PREC, NT, NV, true, true>);
-    return reinterpret_cast<const void*>(&contract_kernel<PREC, NT, NV, false, false>);
+    if (c) return contract_entry<PREC, NT, NV, true, true>();
+    return contract_entry<PREC, NT, NV, false, false>();
   };
   if constexpr (PREC == MTK_FP8_E4M3) {
     if (p.nv == 32) return pick(std::integral_constant<int, 32>{});
@@ -842,7 +955,7 @@ const void* kernel_of_prec(const ContractPlan& p) {
     case 3: return kernel_of_nt<PREC, 3>(p);
     case 4: return kernel_of_nt<PREC, 4>(p);
   }
-  if constexpr (PREC != MTK_FP8_E4M3) {
+  if (PREC != MTK_FP8_E4M3 || MTK_FP8_NTW > 4) {
     switch (p.ntw) {
       case 5: return kernel_of_nt<PREC, 5>(p);
       case 6: return kernel_of_nt<PREC, 6>(p);
