@@ -141,13 +141,15 @@ def test_fp8_quantize_bit_exact(ctx):
     assert np.array_equal(host(q), qo)
 
 
-# Lanes hold 32, 64 or 128 values as 16-byte pieces; the last four cases have
-# long reductions (608: 16-byte loads, 600: byte loads; 528 in mode 3, also
-# strided) so that 64- and 128-value lanes (R <= 32) and a ragged last window
-# are exercised.
+# Lanes hold 32, 64 or 128 values as 16-byte pieces; the cases with long
+# reductions (608: 16-byte loads, 600: byte loads; 528 in mode 3, also
+# strided) exercise 64- and 128-value lanes (R <= 32) and a ragged last
+# window.  Ranks above 64 run one wave of up to eight column tiles: R = 100
+# (seven tiles, the last one partial) on rows of 70 bytes (byte-wise loads
+# in every mode) and R = 72 (five tiles) with a ragged third window.
 @pytest.mark.parametrize("dims,R", [((40, 33, 50), 16), ((64, 64, 160), 128), ((31, 70, 130), 40),
                                     ((20, 24, 608), 16), ((20, 24, 608), 32), ((18, 22, 600), 32),
-                                    ((12, 528, 20), 16)])
+                                    ((12, 528, 20), 16), ((33, 40, 70), 100), ((48, 40, 272), 72)])
 def test_fp8_mttkrp(ctx, dims, R):
     from gpu_util import dev, host, rel
     X, facs = _sliced_case(dims, R, seed=11)
