@@ -18,6 +18,13 @@ namespace mtk {
 hipError_t launch_extrapolate(const int64_t dims[3], int R, int mode, const float* P, const float* Q, double d,
                               float* factor_out, double* lambda, int64_t maxdim, void* ws, int* status,
                               hipStream_t st);
+// Mode-1 MTTKRP from the Y kernel's row sums, Y not stored (dimtree.hip):
+// its J-block partial slices (0: J does not fit the kernel's row blocks),
+// their scratch, and the launch (plus the slice reduction).
+int64_t ttm_m1_slices(const int64_t dims[3], int R);
+size_t ttm_m1_ws_bytes(const int64_t dims[3], int R);
+hipError_t launch_ttm_m1(const float* X, bool x_aligned16, const int64_t dims[3], const float* const factors[3],
+                         int R, int prec, float* out, void* ws, hipStream_t st, const FactorArgs* job);
 }  // namespace mtk
 
 namespace {
@@ -128,7 +135,21 @@ mtk_status check_prec(mtk_ctx* c, const mtk_tensor* X, int prec) {
   return MTK_OK;
 }
 
+// Mode 1 of an FP32 tensor in bf16x3 whose mode-1 slices are far apart
+// (J*K >= 65536 elements): the contraction's 16-row tiles would read 16
+// rows J*K apart (1024^3: 5.2 TB/s for such a pattern against 6.0 TB/s for
+// rows K apart), so the Y kernel's row sums serve it instead, with Y not
+// stored, reading X row by row (1024^3 R=64: 943-958 -> 876 us).  FP32 is
+// MFMA-bound there, and bf16x6 came out slower and, summing a workgroup's
+// rows in FP32, at twice its error; both keep the contraction.
+static bool m1_route(const int64_t dims[3], int R, int mode, int fmt, int prec) {
+  return mode == 0 && fmt == MTK_FP32 && prec == MTK_BF16X3 &&
+         mtk::ttm_m1_slices(dims, R) > 0 && dims[0] * dims[1] <= mtk::kDimtreeMaxRows &&
+         dims[1] * dims[2] >= 65536;
+}
+
 size_t mttkrp_ws(const int64_t dims[3], int R, int mode, int prec) {
+  if (m1_route(dims, R, mode, MTK_FP32, prec)) return mtk::ttm_m1_ws_bytes(dims, R);
   size_t b = 0;
   for (int tr = 0; tr < 2; ++tr)
     for (int al = 0; al < 2; ++al)
@@ -306,6 +327,12 @@ mtk_status mtk_quantize_fp8(mtk_ctx* c, const float* x, const int64_t dims[3], u
 static mtk_status mttkrp_impl(mtk_ctx* c, const mtk_tensor* X, const float* const factors[3], int R, int mode,
                               int prec, float* out, void* ws, hipStream_t st,
                               const mtk::FactorArgs* job = nullptr) {
+  if (m1_route(X->dims, R, mode, X->fmt, prec)) {
+    hipError_t e = mtk::launch_ttm_m1(static_cast<const float*>(X->data), aligned16(X->data), X->dims, factors, R,
+                                      prec, out, ws, st, job);
+    if (e != hipSuccess) return hip_fail(c, e, "mttkrp launch");
+    return MTK_OK;
+  }
   const float* fr;     // fragment factor (inside the MFMA)
   const float* wt;     // weight factor (epilogue)
   if (mode == 0) { fr = factors[2]; wt = factors[1]; }
@@ -352,7 +379,8 @@ mtk_status mttkrp_noalloc(mtk_ctx* c, const mtk_tensor* X, const float* const fa
   // partial slices and FP8 fragment codes must fit the static scratch.
   const bool tr = mode == 2 && X->fmt == MTK_FP8_E4M3 && X->data_t != nullptr;
   const ContractPlan p = mtk::make_plan(X->dims, (int)R, mode, prec, aligned16(tr ? X->data_t : X->data), tr);
-  const size_t need = mtk::contract_ws_bytes(p, prec);
+  const size_t need = m1_route(X->dims, (int)R, mode, X->fmt, prec) ? mtk::ttm_m1_ws_bytes(X->dims, (int)R)
+                                                                     : mtk::contract_ws_bytes(p, prec);
   if (need > kNoAllocScratchBytes)
     return fail(c, MTK_EUNSUPPORTED, "mttkrp_noalloc: this shape needs " + std::to_string(need) +
                                          " bytes of scratch, above the " + std::to_string(kNoAllocScratchBytes) +

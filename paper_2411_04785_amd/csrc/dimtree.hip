@@ -221,18 +221,21 @@ __global__ __launch_bounds__(256) void ttm_kernel(TtmArgs a) {
   if (p0 + 16 * RT <= a.P && K % KW == 0) run(std::true_type{});
   else run(std::false_type{});
 
+  // Y itself (not stored when only its row sums are asked for: a.Y null).
+  if (a.Y) {
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int col = t * 16 + n;
-      if (col >= R) continue;
+      for (int t = 0; t < NT; ++t) {
+        const int col = t * 16 + n;
+        if (col >= R) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = p0 + rt * 16 + g * 4 + v;
-        if (row < a.P) a.Y[row * R + col] = acc[rt][t][v];
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = p0 + rt * 16 + g * 4 + v;
+          if (row < a.P) a.Y[row * R + col] = acc[rt][t][v];
+        }
       }
-    }
+  }
 
   if (a.B) {
     // All rows of the workgroup have the same i (the launcher checks J).
@@ -368,6 +371,48 @@ int64_t ttm_fused_slices(const int64_t dims[3], int R) {
 }
 
 }  // namespace
+
+// Mode-1 MTTKRP from the Y kernel's row sums with Y itself not stored:
+// M1(i, r) = sum_j B(j, r) sum_k X(i, j, k) C(k, r), each workgroup's rows
+// (one i, a block of j) summed inside it in fixed order, then the J blocks'
+// partial rows added in order.  X is read row by row (rows of K elements),
+// where the contraction's 16-row tiles would take rows J*K apart.  For J a
+// multiple of the kernel's rows per workgroup (m1_slices > 0); `ws` holds
+// m1_ws_bytes.
+int64_t ttm_m1_slices(const int64_t dims[3], int R) { return ttm_fused_slices(dims, R); }
+
+size_t ttm_m1_ws_bytes(const int64_t dims[3], int R) {
+  const int64_t s = ttm_fused_slices(dims, R);
+  return s > 1 ? r256((size_t)s * dims[0] * R * sizeof(float)) : 0;
+}
+
+hipError_t launch_ttm_m1(const float* X, bool x_aligned16, const int64_t dims[3], const float* const factors[3],
+                         int R, int prec, float* out, void* ws, hipStream_t st, const FactorArgs* job) {
+  const int64_t fused = ttm_fused_slices(dims, R);
+  if (fused < 1 || (prec != MTK_FP32 && prec != MTK_BF16X3 && prec != MTK_BF16X6) || R < 1 || R > kMaxRank ||
+      dims[0] * dims[1] > kDimtreeMaxRows || (job && (job->R > kJobMaxRank || R > 32)))
+    return hipErrorInvalidValue;
+  TtmArgs t{};
+  t.X = X;
+  t.C = factors[2];
+  t.Y = nullptr;
+  t.P = dims[0] * dims[1];
+  t.K = (int)dims[2];
+  t.R = R;
+  t.job_on = job ? 1 : 0;
+  if (job) t.job = *job;
+  t.B = factors[1];
+  t.m1part = fused > 1 ? static_cast<float*>(ws) : out;
+  t.J = (int)dims[1];
+  t.I = dims[0];
+  const bool vec = x_aligned16 && dims[2] % 4 == 0;
+  hipError_t e = prec == MTK_FP32     ? launch_ttm_prec<MTK_FP32>(t, vec, st)
+                 : prec == MTK_BF16X3 ? launch_ttm_prec<MTK_BF16X3>(t, vec, st)
+                                      : launch_ttm_prec<MTK_BF16X6>(t, vec, st);
+  if (e != hipSuccess) return e;
+  if (fused > 1) return launch_slice_reduce(static_cast<float*>(ws), (int)fused, dims[0] * R, out, st);
+  return hipSuccess;
+}
 
 bool dimtree_used(const int64_t dims[3], int R, int prec) {
   // Y costs one write and two reads of I*J*R floats against the saved pass

@@ -278,6 +278,38 @@ def test_dimtree_matches_oracle(ctx, prec, dims, R):
         assert rel(got, ref) <= TOL[prec], (mode, rel(got, ref))
 
 
+# Mode 0 (the paper's mode 1) of an FP32 tensor in bf16x3 with J a multiple
+# of the Y kernel's rows per workgroup and J*K >= 65536: mttkrp takes the Y
+# kernel's row sums with Y not stored.  The same kernel and
+# summation as mttkrp_dimtree's mode 0 (which also stores Y), so the two
+# agree bit for bit, as does mttkrp_noalloc; against the oracle the usual
+# bar.  R = 100 and 128 take 128-row workgroups (two or six J slices); the
+# unaligned K = 257 takes the byte-wise loads; (5, 256, 255) falls just
+# below the J*K threshold and keeps the contraction.
+M1_ROUTE = [((8, 256, 256), 16), ((5, 512, 130), 64), ((4, 256, 257), 32), ((3, 256, 300), 100),
+            ((2, 768, 96), 128), ((5, 256, 255), 48)]
+
+
+@pytest.mark.parametrize("prec", ["bf16x3"])
+@pytest.mark.parametrize("dims,R", M1_ROUTE)
+def test_mode1_row_sum_route(ctx, prec, dims, R):
+    import torch
+    from gpu_util import dev, host, rel
+    X, facs = _case(dims, R, seed=sum(dims) + 3 * R)
+    Xd, fd = dev(X), [dev(f) for f in facs]
+    _say("mode-1 row-sum route", prec, dims, R)
+    got = host(ctx.mttkrp(Xd, fd, 0, prec))
+    ref = oracle.mttkrp(X, facs, 0)
+    assert rel(got, ref) <= TOL[prec], rel(got, ref)
+    rows = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert rows.max() <= 4 * TOL[prec], rows.max()
+    out = torch.empty((dims[0], R), dtype=torch.float32, device=Xd.device)
+    ctx.mttkrp_noalloc(Xd, fd, 0, out, prec)
+    assert np.array_equal(host(out), got)
+    if dims[1] * dims[2] >= 65536:
+        assert np.array_equal(host(ctx.mttkrp_dimtree(Xd, fd, 0, prec)), got)
+
+
 def test_dimtree_deterministic_and_rejects(ctx):
     from gpu_util import dev, host
     from paper_2411_04785_amd.mttkrp import MtkError
