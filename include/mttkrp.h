@@ -136,7 +136,9 @@ mtk_status mtk_quantize_fp8(mtk_ctx* ctx, const float* x, const int64_t dims[3],
  *             an FP8 tensor (the tensor's fmt decides; prec must match).
  *  out      : device FP32, dims[mode] x R row-major; fully overwritten.
  * The result is deterministic: the summation order depends only on
- * (dims, R, mode, prec), never on timing or on other work on the device. */
+ * (dims, R, mode, prec), never on timing or on other work on the device.
+ * (bf16x3 mode 0 with J a multiple of 256 -- 128 above R = 64 -- and
+ * J*K >= 65536 is formed as mttkrp_dimtree's mode 0, bit for bit.) */
 mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
                   int64_t R, int mode, int prec, float* out, void* stream);
 
@@ -144,7 +146,8 @@ mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, kernels, plan and result (bit for bit)
  * as mttkrp; the caller passes X, the factors and out as before.  The
- * split-K partial slices and FP8 fragment codes go to a static device
+ * split-K partial slices (for bf16x3 mode 0 as above, the J-block partial
+ * rows) and FP8 fragment codes go to a static device
  * buffer of 64 MiB (one per device, held from library load until the
  * process ends) instead of the context's workspace, and the call makes no
  * hipMalloc, hipFree or other allocating call.  Nothing in the buffer needs
