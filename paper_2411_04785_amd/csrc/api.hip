@@ -693,14 +693,18 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
       if (e != hipSuccess) return hip_fail(c, e, "update launch");
       continue;
     }
+    // The fork is recorded before the MTTKRP, but the MTTKRP is enqueued
+    // first: in a captured graph the runtime keeps a node's first child on
+    // its queue, so the MTTKRP and the update stay on one queue and only
+    // the factorisation crosses over (and usually ends before the MTTKRP).
     HIP_OR_FAIL(c, hipEventRecord(c->fork_ev[n], st));
+    mtk::MSlices ms;
+    mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, cws, dt_ws, st, &ms);
+    if (s != MTK_OK) return s;
     HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->fork_ev[n], 0));
     hipError_t e = mtk::launch_factor(X->dims, R, n, maxdim, solve_ws, c->d_status, c->side);
     if (e != hipSuccess) return hip_fail(c, e, "factorisation launch");
     HIP_OR_FAIL(c, hipEventRecord(c->join_ev[n], c->side));
-    mtk::MSlices ms;
-    mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, cws, dt_ws, st, &ms);
-    if (s != MTK_OK) return s;
     HIP_OR_FAIL(c, hipStreamWaitEvent(st, c->join_ev[n], 0));
     e = mtk::launch_apply(X->dims, R, n, ms, factors[n], lambda, maxdim, solve_ws, c->d_status, st, n == 2);
     if (e != hipSuccess) return hip_fail(c, e, "update launch");
