@@ -673,6 +673,7 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
   void* dt_ws = sweep_dimtree_ws(c, X->dims, R, prec);
   const float* cf[3] = {factors[0], factors[1], factors[2]};
   const bool overlap = R >= kOverlapMinRank;
+  const bool tree = mtk::dimtree_used(X->dims, R, prec);
   for (int n = 0; n < 3; ++n) {
     if (R <= mtk::kJobMaxRank) {
       const mtk::FactorArgs f = mtk::factor_args(X->dims, R, n, maxdim, solve_ws, c->d_status);
@@ -693,18 +694,29 @@ static mtk_status enqueue_sweep(mtk_ctx* c, const mtk_tensor* X, float* const fa
       if (e != hipSuccess) return hip_fail(c, e, "update launch");
       continue;
     }
-    // The fork is recorded before the MTTKRP, but the MTTKRP is enqueued
-    // first: in a captured graph the runtime keeps a node's first child on
-    // its queue, so the MTTKRP and the update stay on one queue and only
-    // the factorisation crosses over (and usually ends before the MTTKRP).
+    // In a captured graph the runtime keeps a node's first-captured child
+    // on its queue.  With the dimension tree the MTTKRPs (the Y kernel, the
+    // mode-3 contraction) run far longer than the factorisation: the MTTKRP
+    // is enqueued first (the fork still recorded before it), so it and the
+    // update stay on one queue and only the factorisation crosses over.
+    // With three contractions (FP8; short K) an MTTKRP takes about as long
+    // as the factorisation, which then needs a free CU at the start (on a
+    // full GPU it runs twice as long): the factorisation is enqueued first.
+    const bool mttkrp_first = tree;
     HIP_OR_FAIL(c, hipEventRecord(c->fork_ev[n], st));
     mtk::MSlices ms;
-    mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, cws, dt_ws, st, &ms);
-    if (s != MTK_OK) return s;
+    if (mttkrp_first) {
+      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, cws, dt_ws, st, &ms);
+      if (s != MTK_OK) return s;
+    }
     HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->fork_ev[n], 0));
     hipError_t e = mtk::launch_factor(X->dims, R, n, maxdim, solve_ws, c->d_status, c->side);
     if (e != hipSuccess) return hip_fail(c, e, "factorisation launch");
     HIP_OR_FAIL(c, hipEventRecord(c->join_ev[n], c->side));
+    if (!mttkrp_first) {
+      mtk_status s = sweep_mttkrp(c, X, cf, R, n, prec, M, cws, dt_ws, st, &ms);
+      if (s != MTK_OK) return s;
+    }
     HIP_OR_FAIL(c, hipStreamWaitEvent(st, c->join_ev[n], 0));
     e = mtk::launch_apply(X->dims, R, n, ms, factors[n], lambda, maxdim, solve_ws, c->d_status, st, n == 2);
     if (e != hipSuccess) return hip_fail(c, e, "update launch");
