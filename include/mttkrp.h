@@ -137,8 +137,9 @@ mtk_status mtk_quantize_fp8(mtk_ctx* ctx, const float* x, const int64_t dims[3],
  *  out      : device FP32, dims[mode] x R row-major; fully overwritten.
  * The result is deterministic: the summation order depends only on
  * (dims, R, mode, prec), never on timing or on other work on the device.
- * (bf16x3 mode 0 with J a multiple of 256 -- 128 above R = 64 -- and
- * J*K >= 65536 is formed as mttkrp_dimtree's mode 0, bit for bit.) */
+ * (bf16x3 mode 0 with J a multiple of 256 -- 128 above R = 64 --,
+ * K >= 512 and J*K >= 65536 is formed as mttkrp_dimtree's mode 0, bit for
+ * bit.) */
 mtk_status mttkrp(mtk_ctx* ctx, const mtk_tensor* X, const float* const factors[3],
                   int64_t R, int mode, int prec, float* out, void* stream);
 

@@ -279,15 +279,15 @@ def test_dimtree_matches_oracle(ctx, prec, dims, R):
 
 
 # Mode 0 (the paper's mode 1) of an FP32 tensor in bf16x3 with J a multiple
-# of the Y kernel's rows per workgroup and J*K >= 65536: mttkrp takes the Y
-# kernel's row sums with Y not stored.  The same kernel and
+# of the Y kernel's rows per workgroup, K >= 512 and J*K >= 65536: mttkrp
+# takes the Y kernel's row sums with Y not stored.  The same kernel and
 # summation as mttkrp_dimtree's mode 0 (which also stores Y), so the two
 # agree bit for bit, as does mttkrp_noalloc; against the oracle the usual
 # bar.  R = 100 and 128 take 128-row workgroups (two or six J slices); the
-# unaligned K = 257 takes the byte-wise loads; (5, 256, 255) falls just
-# below the J*K threshold and keeps the contraction.
-M1_ROUTE = [((8, 256, 256), 16), ((5, 512, 130), 64), ((4, 256, 257), 32), ((3, 256, 300), 100),
-            ((2, 768, 96), 128), ((5, 256, 255), 48)]
+# unaligned K = 513 takes the byte-wise loads; (5, 256, 511) falls just
+# below the K threshold and keeps the contraction.
+M1_ROUTE = [((4, 256, 512), 16), ((3, 512, 520), 64), ((3, 256, 513), 32), ((2, 256, 600), 100),
+            ((2, 768, 512), 128), ((5, 256, 511), 48)]
 
 
 @pytest.mark.parametrize("prec", ["bf16x3"])
@@ -306,7 +306,7 @@ def test_mode1_row_sum_route(ctx, prec, dims, R):
     out = torch.empty((dims[0], R), dtype=torch.float32, device=Xd.device)
     ctx.mttkrp_noalloc(Xd, fd, 0, out, prec)
     assert np.array_equal(host(out), got)
-    if dims[1] * dims[2] >= 65536:
+    if dims[1] * dims[2] >= 65536 and dims[2] >= 512:
         assert np.array_equal(host(ctx.mttkrp_dimtree(Xd, fd, 0, prec)), got)
 
 

@@ -47,6 +47,10 @@ NWAY = [
     ((2, 2, 3, 2, 3, 2, 4), 4),
     ((96, 80, 64, 48), 32),
     ((7, 300, 5, 9), 64),
+    # Long trailing modes: the three-way views of the first mode are
+    # (2, 16, 4096) and (3, 16, 4096).
+    ((2, 16, 32, 128), 16),
+    ((3, 16, 32, 128), 48),
 ]
 
 
