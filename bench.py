@@ -380,6 +380,8 @@ def sparse_bench(args):
     mode_ms, outs = [], []
     for mode in range(3):
         out = ctx.mttkrp_coo(t, f0, mode)
+        if mode == 0:
+            gpu_warm(torch, lambda: ctx.mttkrp_coo(t, f0, 0, out=out))
         mode_ms.append(time_calls(torch, stream, lambda: ctx.mttkrp_coo(t, f0, mode, out=out), args.mode_reps))
         outs.append(out.cpu().numpy().astype(np.float64))
         log(f"[bench] mode {mode}: {mode_ms[-1] * 1e3:.1f} us per sparse MTTKRP")
@@ -476,6 +478,8 @@ def nway_bench(args):
         mode_ms, outs = [], []
         for mode in range(n):
             out = ctx.mttkrp_nway(Xd, f0, mode, p)
+            if mode == 0:
+                gpu_warm(torch, lambda: ctx.mttkrp_nway(Xd, f0, 0, p, out=out))
             mode_ms.append(time_calls(torch, stream, lambda: ctx.mttkrp_nway(Xd, f0, mode, p, out=out),
                                       args.mode_reps))
             outs.append(out.cpu().numpy().astype(np.float64))
@@ -537,6 +541,17 @@ def _events(torch, stream):
     return e0, e1
 
 
+def gpu_warm(torch, fn, seconds=0.25):
+    """Call fn until `seconds` have passed (then synchronise): brings the
+    device out of the idle state it sits in while inputs are generated, so
+    that the first mode timed is not slower than the others."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(4):
+            fn()
+        torch.cuda.synchronize()
+
+
 def time_calls(torch, stream, fn, reps, warm=10):
     """Average ms of fn() over `reps` back-to-back calls, HIP events on the
     library's stream, after `warm` untimed calls (steady clocks, page tables)."""
@@ -558,6 +573,8 @@ def run_path(ctx, torch, stream, w, prec, X_run, kw, f0, args):
     mode_ms, outs = [], []
     for mode in range(3):
         out = ctx.mttkrp(X_run, f0, mode, prec, **kw)
+        if mode == 0:
+            gpu_warm(torch, lambda: ctx.mttkrp(X_run, f0, 0, prec, out=out, **kw))
         mode_ms.append(time_calls(torch, stream, lambda: ctx.mttkrp(X_run, f0, mode, prec, out=out, **kw),
                                   args.mode_reps))
         outs.append(out.cpu().numpy())

@@ -139,13 +139,17 @@ mtk_status check_prec(mtk_ctx* c, const mtk_tensor* X, int prec) {
 // (J*K >= 65536 elements): the contraction's 16-row tiles would read 16
 // rows J*K apart (1024^3: 5.2 TB/s for such a pattern against 6.0 TB/s for
 // rows K apart), so the Y kernel's row sums serve it instead, with Y not
-// stored, reading X row by row (1024^3 R=64: 943-958 -> 852-876 us).  Rows
-// must be long (K >= 512): on rows of 128 elements the Y kernel's per-row
-// work outweighs the gain (128 x 16384 x 128, R=32: 207 against 188 us).
-// FP32 is MFMA-bound there, and bf16x6 came out slower and, summing a
-// workgroup's rows in FP32, at twice its error; both keep the contraction.
+// stored, reading X row by row (1024^3 R=64, same device: 932 -> 776 us;
+// MTK_M1_ROUTE=0 builds without it).  Rows must be long (K >= 512): on
+// rows of 128 elements the Y kernel's per-row work outweighs the gain
+// (128 x 16384 x 128, R=32: 207 against 188 us).  FP32 is MFMA-bound
+// there, and bf16x6 came out slower and, summing a workgroup's rows in
+// FP32, at twice its error; both keep the contraction.
+#ifndef MTK_M1_ROUTE
+#define MTK_M1_ROUTE 1
+#endif
 static bool m1_route(const int64_t dims[3], int R, int mode, int fmt, int prec) {
-  return mode == 0 && fmt == MTK_FP32 && prec == MTK_BF16X3 &&
+  return MTK_M1_ROUTE && mode == 0 && fmt == MTK_FP32 && prec == MTK_BF16X3 &&
          mtk::ttm_m1_slices(dims, R) > 0 && dims[0] * dims[1] <= mtk::kDimtreeMaxRows &&
          dims[1] * dims[2] >= 65536 && dims[2] >= 512;
 }
